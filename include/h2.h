@@ -1,0 +1,149 @@
+/*
+ * h2.h -- C ABI of the MI355X H^2 matrix-vector product library (libh2gemv.so).
+ *
+ * The library applies one H^2 matrix
+ *     A = A_de + <U, S, V^T>                      (Section 2.1 of the paper)
+ * to a block of nv vectors on one GPU:
+ *     Y <- alpha * op(A) * X + beta * Y,   op(A) = A or A^T,
+ * by the three phases of Section 3 -- the upsweep of the column basis tree
+ * (x^ = V^T x, Section 3.1 / Algorithm 1), the level-wise coupling product
+ * (y^ = S x^, Section 3.2 / Algorithm 4), the downsweep of the row basis
+ * tree (y = U y^, Section 3.3 / Algorithm 6) -- plus the block-sparse product
+ * with the dense leaf blocks A_de (Section 3).  The operator's data comes
+ * from the serialized representation "H2MATV01" (layout documented in the
+ * design notes and in h2gen/fmt.py): cluster tree, permutation, per-level
+ * ranks, leaf bases U (and V), transfers E (and F), coupling blocks S in CSR
+ * per level, dense blocks D in CSR over leaves, all FP64, column-major.
+ *
+ * Conventions for every entry point
+ *   - Return value: H2_OK (0) or a negative H2_E* code; on error a message is
+ *     available from h2_last_error() in the calling thread.
+ *   - No entry point throws or aborts; HIP errors are reported as H2_EHIP.
+ *   - Handles own all device memory they allocate; callers own X and Y.
+ */
+#ifndef H2_H_
+#define H2_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_op_s* h2_handle;
+
+enum {
+  H2_OK = 0,
+  H2_EINVAL = -1,      /* bad argument: NULL handle or pointer, bad op, nv < 0,
+                          leading dimension < n, X and Y overlap */
+  H2_EIO = -2,         /* file could not be read */
+  H2_EFORMAT = -3,     /* not a valid representation (magic, version, sizes,
+                          tree, permutation, CSR structure) */
+  H2_ENOMEM = -4,      /* host or device allocation failed */
+  H2_EHIP = -5,        /* other HIP runtime error (message has the HIP text) */
+  H2_EUNSUPPORTED = -6 /* valid, but outside this build's limits (a rank or a
+                          leaf size above 256, n >= 2^31) */
+};
+
+/* Structure and algorithmic work of a loaded operator.  "entries" count the
+ * stored FP64 values of each part; when V, F are shared with U, E they are
+ * still counted, because the product reads them in both sweeps. */
+typedef struct {
+  int64_t n;              /* matrix order */
+  int64_t depth;          /* leaf level q (root is level 0) */
+  int64_t nnodes;         /* cluster-tree nodes */
+  int64_t nleaves;        /* leaves (nodes of level q) */
+  int64_t ncoupling;      /* coupling blocks, all levels */
+  int64_t ndense;         /* dense leaf blocks */
+  int64_t csp;            /* largest number of coupling blocks in a block row
+                             or column of any level (sparsity constant) */
+  int64_t csp_dense;      /* largest number of dense blocks in a leaf row/column */
+  int64_t entries_U, entries_V, entries_E, entries_F, entries_S, entries_D;
+  int64_t tree_rows;      /* sum over nodes of the node's rank: the length of
+                             the vector trees x^ and y^ for one vector */
+  int64_t shared_basis;   /* 1 when V = U and F = E */
+  int64_t device_bytes;   /* device memory held by the handle now */
+  int64_t max_rank;       /* largest rank of any level */
+  int64_t max_leaf;       /* largest leaf size */
+} h2_stats_t;
+
+/* Per-phase GPU time accumulated over the h2_gemv calls made while profiling
+ * was on (h2_profile), measured with HIP events recorded on the stream each
+ * phase runs on.  Times in milliseconds. */
+typedef struct {
+  int64_t calls;          /* h2_gemv calls profiled */
+  double ms_permute;      /* input permutation into tree order */
+  double ms_upsweep;      /* leaf products V^T x and transfer upsweep */
+  double ms_coupling;     /* coupling products, all levels */
+  double ms_downsweep;    /* transfer downsweep */
+  double ms_dense;        /* dense near-field blocks */
+  double ms_leaf_out;     /* leaf expansion U y^ and the alpha/beta update */
+  double ms_total;        /* first to last event of each call, summed */
+} h2_profile_t;
+
+/* Load the representation stored in the file at `path` onto GPU `device`
+ * (a HIP device ordinal) and build the launch schedules.  On success *out
+ * receives a handle that owns all device memory.  Errors: H2_EINVAL,
+ * H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED. */
+int h2_load(const char* path, int device, h2_handle* out);
+
+/* As h2_load, from a host buffer of `len` bytes holding the serialized
+ * representation (8-byte aligned).  The buffer is only read during the
+ * call; the caller keeps ownership. */
+int h2_load_mem(const void* buf, size_t len, int device, h2_handle* out);
+
+/* Validate a serialized representation on the host only (no GPU is
+ * touched).  Returns H2_OK, H2_EINVAL, H2_EFORMAT or H2_EUNSUPPORTED. */
+int h2_validate(const void* buf, size_t len);
+
+/* Y <- alpha * op(A) * X + beta * Y on the handle's GPU.
+ *   op      'N' (A) or 'T' (A^T), either case.
+ *   X, Y    DEVICE pointers, caller-owned, FP64, column-major n x nv with
+ *           leading dimensions ldx, ldy >= n, rows in the ORIGINAL point
+ *           order (the library applies the tree permutation).  X is read
+ *           only; X and Y must not overlap.
+ *   nv      number of vectors, >= 0; nv == 0 returns H2_OK with no work.
+ *   alpha   alpha == 0 means Y <- beta * Y and X is not read.
+ *   beta    beta == 0 means Y is overwritten and not read (NaN-safe).
+ *   stream  hipStream_t to enqueue on (NULL = the device's null stream).
+ * Asynchronous: returns after enqueueing.  Results are deterministic
+ * (no floating-point atomics).  A handle's workspace is shared: calls on
+ * one handle must not run concurrently on different streams.  The workspace
+ * grows on demand (device allocation) unless h2_reserve sized it first;
+ * nv above 64 is processed in chunks of 64 vectors.
+ * Errors: H2_EINVAL, H2_ENOMEM, H2_EHIP. */
+int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
+            double beta, double* Y, int64_t ldy, void* stream);
+
+/* Pre-size the workspace for up to nv_max vectors per call (capped at the
+ * 64-vector chunk), so that later h2_gemv calls allocate nothing. */
+int h2_reserve(h2_handle h, int64_t nv_max);
+
+/* Fill *st with the operator's structure and stored-entry counts. */
+int h2_stats(h2_handle h, h2_stats_t* st);
+
+/* Matrix order n of a loaded operator, or -1 for a NULL handle. */
+int64_t h2_n(h2_handle h);
+
+/* Turn per-phase event timing of h2_gemv on (enable != 0) or off, and reset
+ * the accumulated times.  Off by default. */
+int h2_profile(h2_handle h, int enable);
+
+/* Synchronize on the recorded events and return the accumulated per-phase
+ * times since profiling was last enabled. */
+int h2_profile_read(h2_handle h, h2_profile_t* out);
+
+/* Release the handle and its device memory (synchronizes the device first).
+ * h2_free(NULL) is a no-op returning H2_OK. */
+int h2_free(h2_handle h);
+
+/* Message of the last error in the calling thread ("" if none).  The string
+ * is owned by the library and valid until the next call in that thread. */
+const char* h2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2_H_ */

@@ -35,6 +35,8 @@ def _load():
         lib.h2o_gemv.restype = ci
         lib.h2o_gemv_rows.argtypes = [vp, ch, dbl, vp, i64, i64, dbl, vp, i64, vp, i64, vp, ci]
         lib.h2o_gemv_rows.restype = ci
+        lib.h2o_threads.argtypes = []
+        lib.h2o_threads.restype = ci
         lib.h2o_dense.argtypes = [vp, ch, vp]
         lib.h2o_dense.restype = ci
         _lib = lib
@@ -108,6 +110,11 @@ class Oracle:
         if rc != 0:
             raise OracleError(f"h2o_dense failed ({rc})")
         return A
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().h2o_threads())
 
 
 def open_rep(buf) -> Oracle:

@@ -327,6 +327,15 @@ fail:
 
 int64_t h2o_n(const h2o_rep* r) { return r ? r->n : -1; }
 
+/* Threads the oracle's parallel loops use. */
+int h2o_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* the product                                                              */
 /* ------------------------------------------------------------------------ */

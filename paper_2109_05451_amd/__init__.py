@@ -1,0 +1,182 @@
+"""MI355X H^2 matrix-vector product: Python binding of libh2gemv.so.
+
+Argument marshalling only.  Every step of the product runs in the HIP
+kernels of ``libh2gemv.so`` behind the C ABI of ``include/h2.h``; PyTorch is
+used for device memory and streams.  There is no CPU fallback: if the library
+is not built, importing works but constructing an operator raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2gemv.so")
+
+H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+# exported symbols of include/h2.h, in declaration order
+EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_reserve", "h2_stats", "h2_n",
+           "h2_profile", "h2_profile_read", "h2_free", "h2_last_error")
+
+
+class H2Stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "depth", "nnodes", "nleaves", "ncoupling", "ndense", "csp", "csp_dense",
+        "entries_U", "entries_V", "entries_E", "entries_F", "entries_S", "entries_D",
+        "tree_rows", "shared_basis", "device_bytes", "max_rank", "max_leaf")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class H2Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64)] + [(name, ctypes.c_double) for name in (
+        "ms_permute", "ms_upsweep", "ms_coupling", "ms_downsweep", "ms_dense", "ms_leaf_out", "ms_total")]
+
+    def as_dict(self):
+        return {name: (int if name == "calls" else float)(getattr(self, name)) for name, _ in self._fields_}
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libh2gemv error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libh2gemv.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() -- there is no fallback")
+    lib = ctypes.CDLL(path)
+    vp, i64, ci, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.h2_load.argtypes = [ctypes.c_char_p, ci, ctypes.POINTER(vp)]
+    lib.h2_load.restype = ci
+    lib.h2_load_mem.argtypes = [vp, ctypes.c_size_t, ci, ctypes.POINTER(vp)]
+    lib.h2_load_mem.restype = ci
+    lib.h2_validate.argtypes = [vp, ctypes.c_size_t]
+    lib.h2_validate.restype = ci
+    lib.h2_gemv.argtypes = [vp, ctypes.c_char, dbl, vp, i64, i64, dbl, vp, i64, vp]
+    lib.h2_gemv.restype = ci
+    lib.h2_reserve.argtypes = [vp, i64]
+    lib.h2_reserve.restype = ci
+    lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
+    lib.h2_stats.restype = ci
+    lib.h2_n.argtypes = [vp]
+    lib.h2_n.restype = i64
+    lib.h2_profile.argtypes = [vp, ci]
+    lib.h2_profile.restype = ci
+    lib.h2_profile_read.argtypes = [vp, ctypes.POINTER(H2Profile)]
+    lib.h2_profile_read.restype = ci
+    lib.h2_free.argtypes = [vp]
+    lib.h2_free.restype = ci
+    lib.h2_last_error.argtypes = []
+    lib.h2_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != H2_OK:
+        raise H2Error(rc, load_library().h2_last_error().decode(errors="replace"))
+
+
+def validate(buf) -> int:
+    """Host-only validation of a serialized representation; returns the code."""
+    b = np.ascontiguousarray(np.asarray(buf).view(np.uint8).ravel())
+    return int(load_library().h2_validate(b.ctypes.data, b.size))
+
+
+class H2Operator:
+    """One H^2 operator resident on a GPU.
+
+    ``src`` is a path to a serialized representation or a uint8 buffer
+    holding one.  ``gemv`` computes Y <- alpha op(A) X + beta Y for device
+    tensors X, Y of shape (n, nv) in column-major layout (stride (1, ld)).
+    """
+
+    def __init__(self, src, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        if isinstance(src, (str, os.PathLike)):
+            _check(lib.h2_load(os.fsencode(src), device, ctypes.byref(h)))
+        else:
+            b = np.ascontiguousarray(np.asarray(src).view(np.uint8).ravel())
+            _check(lib.h2_load_mem(b.ctypes.data, b.size, device, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.n = int(lib.h2_n(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().h2_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        st = H2Stats()
+        _check(load_library().h2_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reserve(self, nv_max: int):
+        _check(load_library().h2_reserve(self._h, nv_max))
+
+    def profile(self, enable: bool = True):
+        _check(load_library().h2_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        p = H2Profile()
+        _check(load_library().h2_profile_read(self._h, ctypes.byref(p)))
+        return p.as_dict()
+
+    def gemv_raw(self, op: str, alpha: float, x_ptr: int, ldx: int, nv: int, beta: float, y_ptr: int,
+                 ldy: int, stream: int = 0):
+        """Direct C-ABI call with device pointers (integers)."""
+        _check(load_library().h2_gemv(self._h, op.encode(), float(alpha), x_ptr or None, ldx, nv, float(beta),
+                                      y_ptr or None, ldy, stream or None))
+
+    def gemv(self, X, op: str = "N", alpha: float = 1.0, beta: float = 0.0, Y=None, stream=None):
+        """Y <- alpha op(A) X + beta Y.  X, Y: torch tensors (device or host;
+        host tensors are copied to the operator's device).  Returns Y."""
+        import torch
+        dev = torch.device("cuda", self.device)
+
+        def colmajor(t):
+            t = t.to(device=dev, dtype=torch.float64)
+            if t.dim() == 1:
+                t = t.reshape(-1, 1)
+            if t.shape[0] != self.n:
+                raise ValueError(f"expected {self.n} rows, got {t.shape[0]}")
+            if t.stride(0) != 1 or (t.shape[1] > 1 and t.stride(1) < self.n):
+                t = t.t().contiguous().t()
+            return t
+
+        X = colmajor(X)
+        nv = X.shape[1]
+        if Y is None:
+            Y = torch.empty((nv, self.n), dtype=torch.float64, device=dev).t()
+            beta = 0.0
+        else:
+            Y = colmajor(Y)
+        ldx = X.stride(1) if nv > 1 else self.n
+        ldy = Y.stride(1) if nv > 1 else self.n
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.gemv_raw(op, alpha, X.data_ptr(), ldx, nv, beta, Y.data_ptr(), ldy, s.cuda_stream)
+        return Y
+
+
+__all__ = ["H2Operator", "H2Error", "load_library", "validate", "EXPORTS"]
