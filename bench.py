@@ -49,12 +49,14 @@ def algorithmic(st: dict, nv: int, beta_nonzero: bool = False) -> dict:
             "phase_flops": {"coupling": 2.0 * nv * ent["S"], "dense": 2.0 * nv * ent["D"]}}
 
 
-def time_gpu(g, X, Y, nv, steps, warmup, torch):
+def time_gpu(g, X, Y, nv, steps, warmup, torch, precision="fp64"):
     n = g.n
     stream = torch.cuda.current_stream()
     g.reserve(nv)
+    if precision != "fp64":
+        g.prepare(precision)
     for _ in range(warmup):
-        g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream)
+        g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream, precision)
     torch.cuda.synchronize()
     g.profile(True)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -63,7 +65,7 @@ def time_gpu(g, X, Y, nv, steps, warmup, torch):
     t0 = time.perf_counter()
     for i in range(steps):
         starts[i].record(stream)
-        g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream)
+        g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream, precision)
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -99,6 +101,8 @@ def main():
     ap.add_argument("--nv", type=int, default=None, help="vectors of the headline run (default: config's first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -106,6 +110,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        a = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
+        return
     import h2gen
     from paper_2109_05451_amd import H2Operator
 
@@ -121,52 +134,75 @@ def main():
     st = g.stats()
     print(f"# loaded in {t_load:.1f} s; stats {st}", file=sys.stderr, flush=True)
 
-    nv_list = [nv] + ([v for v in cfg["nv"] if v != nv] if not args.no_variants else [])
-    results = {}
-    for v in nv_list:
+    runs = [(nv, "fp64")]
+    if not args.no_variants:
+        runs += [(v, "fp64") for v in cfg["nv"] if v != nv]
+        runs += [(v, "fp32") for v in cfg["nv"]]
+    results, ref_out = {}, {}
+    for v, prec in runs:
         Xh = h2gen.vectors(g.n, v, cfg["seed_vec"])
         X = torch.from_numpy(np.asfortranarray(Xh)).cuda()
         Y = torch.empty((v, g.n), dtype=torch.float64, device="cuda").t()
-        wall, per_call, prof = time_gpu(g, X, Y, v, args.steps, args.warmup, torch)
+        wall, per_call, prof = time_gpu(g, X, Y, v, args.steps, args.warmup, torch, prec)
         alg = algorithmic(st, v)
         srt = np.sort(per_call)
         trimmed = srt[1:-1] if srt.size > 2 else srt  # the paper drops the fastest and the slowest
         t_ms = float(np.mean(trimmed))
         phases = {k[3:]: prof[k] / prof["calls"] for k in prof if k.startswith("ms_")}
-        results[v] = dict(wall=wall, per_call=per_call, t_ms=t_ms, prof=phases, alg=alg,
-                          p50=float(np.percentile(per_call, 50)), p99=float(np.percentile(per_call, 99)))
-        print(f"# nv={v}: {t_ms:.3f} ms/call, phases {phases}", file=sys.stderr, flush=True)
+        res = dict(wall=wall, per_call=per_call, t_ms=t_ms, prof=phases, alg=alg,
+                   p50=float(np.percentile(per_call, 50)), p99=float(np.percentile(per_call, 99)))
+        Yh = Y.cpu().numpy()
+        if prec == "fp64":
+            ref_out[v] = Yh
+        elif v in ref_out:
+            res["rel_err_vs_fp64"] = float(np.linalg.norm(Yh - ref_out[v]) / np.linalg.norm(ref_out[v]))
+        results[(v, prec)] = res
+        print(f"# nv={v} {prec}: {t_ms:.3f} ms/call, phases {phases}", file=sys.stderr, flush=True)
         del X, Y
 
-    r = results[nv]
+    r = results[(nv, "fp64")]
     alg = r["alg"]
     gflops = alg["flops"] / (r["t_ms"] * 1e-3) / 1e9
-    # dominant kernel: the phase with the most algorithmic bytes among the
-    # single-launch phases (coupling, dense)
+    # dominant kernel: the single-launch phase (coupling or dense) with the most
+    # algorithmic bytes; its bound follows from its arithmetic intensity
     dom = max(("coupling", "dense"), key=lambda k: alg["phase_bytes"][k])
     dom_ms = r["prof"][dom]
-    achieved = alg["phase_bytes"][dom] / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_stream_rows<1> (%s)" % dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": alg["phase_bytes"][dom], "ms_per_launch": round(dom_ms, 4)}
+    ai = alg["phase_flops"][dom] / alg["phase_bytes"][dom]
+    kname = "k_rows_mfma<double>" if nv > 4 else "k_rows<double>"
+    if ai >= FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        achieved = alg["phase_flops"][dom] / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+    else:
+        achieved = alg["phase_bytes"][dom] / (dom_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roofline.update({"traffic": None, "kernel": f"{kname} ({dom} rows)",
+                     "bytes_per_launch": alg["phase_bytes"][dom], "flops_per_launch": alg["phase_flops"][dom],
+                     "ms_per_launch": round(dom_ms, 4)})
     path_gbs = alg["bytes"] / (r["t_ms"] * 1e-3) / 1e9
+    workloads = {
+        "c1_2d_4096": "2D N=4096 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 4x4 (k=16), eta=0.7",
+        "c2_2d_1m": "2D N=2^20 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 6x6 (k=36), eta=0.7",
+        "c3_3d_512k": "3D N=2^19 uniform [0,1]^3, leaf 64, 1/(4 pi r) zero diagonal, Chebyshev 4x4x4 (k=64), eta=0.7",
+    }
     out = {
         "metric": "H2 matvec Gflop/s", "value": round(gflops, 2), "unit": "Gflop/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["t_ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: 2D N=2^20 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 6x6 "
-                               f"(k=36), eta=0.7, nv={nv}, op N, alpha 1, beta 0" if args.config == "c2_2d_1m"
-                   else f"{args.config} nv={nv}",
+        "config": {"workload": f"{args.config}: {workloads.get(args.config, '')}, nv={nv}, op N, alpha 1, beta 0",
                    "n": st["n"], "nv": nv, "coupling_blocks": st["ncoupling"], "dense_blocks": st["ndense"],
                    "csp": st["csp"]},
         "roofline": roofline,
         "path": {"gb_per_s": round(path_gbs, 1), "hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
                  "alg_bytes": alg["bytes"], "alg_flops": alg["flops"], "phases_ms": r["prof"]},
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4), "samples": len(r["per_call"])},
-        "variants": [{"nv": v, "ms": round(results[v]["t_ms"], 4),
-                      "gflops": round(results[v]["alg"]["flops"] / (results[v]["t_ms"] * 1e-3) / 1e9, 2),
-                      "gb_per_s": round(results[v]["alg"]["bytes"] / (results[v]["t_ms"] * 1e-3) / 1e9, 1),
-                      "phases_ms": results[v]["prof"]} for v in nv_list if v != nv],
+        "variants": [{"nv": v, "precision": prec, "ms": round(res["t_ms"], 4),
+                      "gflops": round(res["alg"]["flops"] / (res["t_ms"] * 1e-3) / 1e9, 2),
+                      "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
+                      "rel_err_vs_fp64": res.get("rel_err_vs_fp64"), "p99_ms": round(res["p99"], 4),
+                      "phases_ms": res["prof"]}
+                     for (v, prec), res in results.items() if (v, prec) != (nv, "fp64")],
     }
     if not args.no_cpu:
         Xh = h2gen.vectors(g.n, 1, cfg["seed_vec"])

@@ -46,6 +46,14 @@ enum {
                           leaf size above 256, n >= 2^31) */
 };
 
+/* Precision of the low-rank phases (leaf and transfer sweeps, coupling
+ * products, leaf expansion) in h2_gemv_ex.  The dense near-field products
+ * and the final Y update always run in FP64. */
+enum {
+  H2_PREC_FP64 = 0, /* everything in FP64 */
+  H2_PREC_FP32 = 1  /* low-rank data stored and multiplied in FP32, FP32 accumulation */
+};
+
 /* Structure and algorithmic work of a loaded operator.  "entries" count the
  * stored FP64 values of each part; when V, F are shared with U, E they are
  * still counted, because the product reads them in both sweeps. */
@@ -107,17 +115,34 @@ int h2_validate(const void* buf, size_t len);
  *   alpha   alpha == 0 means Y <- beta * Y and X is not read.
  *   beta    beta == 0 means Y is overwritten and not read (NaN-safe).
  *   stream  hipStream_t to enqueue on (NULL = the device's null stream).
- * Asynchronous: returns after enqueueing.  Results are deterministic
- * (no floating-point atomics).  A handle's workspace is shared: calls on
- * one handle must not run concurrently on different streams.  The workspace
- * grows on demand (device allocation) unless h2_reserve sized it first;
- * nv above 64 is processed in chunks of 64 vectors.
+ * Asynchronous: returns after enqueueing.  The dense near-field phase runs
+ * on a second stream owned by the handle, forked from and joined back to
+ * `stream` with events, so the call is ordered on `stream` like a single
+ * kernel.  Results are deterministic (no floating-point atomics).  A
+ * handle's workspace is shared: calls on one handle must not run
+ * concurrently on different streams.  The workspace is allocated on the
+ * first call unless h2_reserve allocated it first; vectors are processed
+ * in passes of up to 4.
  * Errors: H2_EINVAL, H2_ENOMEM, H2_EHIP. */
 int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
             double beta, double* Y, int64_t ldy, void* stream);
 
-/* Pre-size the workspace for up to nv_max vectors per call (capped at the
- * 64-vector chunk), so that later h2_gemv calls allocate nothing. */
+/* As h2_gemv, with the low-rank phases in precision `prec` (H2_PREC_*).
+ * The reduced-precision copy of the low-rank data is made on the device by
+ * h2_prepare, or by the first call that needs it (device allocation).  The
+ * result differs from the FP64 product by the rounding of the low-rank data
+ * and arithmetic to that precision (about 1e-7 relative for FP32).
+ * Errors: as h2_gemv, plus H2_EINVAL for an unknown precision. */
+int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
+               double beta, double* Y, int64_t ldy, int prec, void* stream);
+
+/* Build the device copy of the low-rank data in precision `prec` now
+ * (no-op for H2_PREC_FP64 or when it exists).  Synchronous. */
+int h2_prepare(h2_handle h, int prec);
+
+/* Allocate the workspace now (it serves any nv), so that later h2_gemv
+ * calls allocate nothing.  nv_max >= 0 is the largest nv the caller plans
+ * to pass. */
 int h2_reserve(h2_handle h, int64_t nv_max);
 
 /* Fill *st with the operator's structure and stored-entry counts. */
@@ -137,6 +162,62 @@ int h2_profile_read(h2_handle h, h2_profile_t* out);
 /* Release the handle and its device memory (synchronizes the device first).
  * h2_free(NULL) is a no-op returning H2_OK. */
 int h2_free(h2_handle h);
+
+/* ---- Cross-operator batching ------------------------------------------
+ * A batch holds several operators in one device arena and applies all of
+ * them in one sequence of launches: the leaf products of every operator in
+ * one launch, then each transfer level of the upsweep aligned by height from
+ * the leaves (Section 3.1, Algorithm 1: uneven trees merge level by level),
+ * the coupling products of every level of every operator in one launch
+ * (Algorithm 4), the downsweep aligned by depth from the root (Algorithm 6),
+ * the dense leaf rows (second stream) and the leaf expansion.  Products run
+ * on the FP64 MFMA row kernels with nv_max vectors per row (padding vectors
+ * are zero); op 'N' only. */
+typedef struct h2_batch_s* h2_batch;
+
+/* One operator's product in a batched call:
+ * Y <- alpha * A_i * X + beta * Y, X and Y device pointers, column-major
+ * n_i x nv in original point order (leading dimensions >= n_i).  nv == 0
+ * skips the operator; alpha == 0 does not read X; beta == 0 does not read Y. */
+typedef struct {
+  const double* X;
+  int64_t ldx;
+  double* Y;
+  int64_t ldy;
+  int64_t nv;       /* 0 <= nv <= the batch's nv_max */
+  double alpha, beta;
+} h2_batch_item;
+
+/* Load `count` serialized representations (bufs[i], lens[i] bytes, host
+ * memory, only read during the call) onto `device` as one batch whose calls
+ * carry at most nv_max (1..64) vectors per operator.  Allocates the arena,
+ * the workspace (sum of 2*(n_i + tree rows_i) * roundup16(nv_max) doubles)
+ * and the merged schedules.  Errors: as h2_load_mem. */
+int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, int64_t nv_max, int device,
+                  h2_batch* out);
+
+/* All products of one call: items[i] belongs to operator i (count items).
+ * Asynchronous on `stream`; the items array is copied during the call.
+ * Errors: H2_EINVAL (bad item), H2_EHIP. */
+int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream);
+
+/* Autotuner: for every merged launch, time each candidate shape (columns
+ * staged per LDS chunk: 32 or 64; workgroups: one per row or a persistent
+ * grid of 1024, 2048 or 4096) on these items and keep the fastest.
+ * Synchronous; the workspace content afterwards is unspecified. */
+int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream);
+
+/* enable != 0: capture the batch's launch sequence into a HIP graph on the
+ * next h2_batch_gemv and replay it on later calls (the item array is still
+ * read afresh every call).  A later h2_batch_tune drops the graph. */
+int h2_batch_graph(h2_batch b, int enable);
+
+/* Number of operators, total order sum n_i, algorithmic flops per vector
+ * (2 * stored entries of all parts) and merged launches per call. */
+int h2_batch_info(h2_batch b, int64_t* count, int64_t* total_n, double* flops_per_vector, int64_t* launches);
+
+/* Release the batch (synchronizes the device first); NULL is a no-op. */
+int h2_batch_free(h2_batch b);
 
 /* Message of the last error in the calling thread ("" if none).  The string
  * is owned by the library and valid until the next call in that thread. */

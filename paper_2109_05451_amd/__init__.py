@@ -19,8 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libh2gemv.so")
 H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 # exported symbols of include/h2.h, in declaration order
-EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_reserve", "h2_stats", "h2_n",
-           "h2_profile", "h2_profile_read", "h2_free", "h2_last_error")
+EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve",
+           "h2_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
+           "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_last_error")
+
+PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
 class H2Stats(ctypes.Structure):
@@ -39,6 +42,11 @@ class H2Profile(ctypes.Structure):
 
     def as_dict(self):
         return {name: (int if name == "calls" else float)(getattr(self, name)) for name, _ in self._fields_}
+
+
+class H2BatchItem(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64),
+                ("nv", ctypes.c_int64), ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class H2Error(RuntimeError):
@@ -67,6 +75,10 @@ def load_library(path: str = LIB_PATH):
     lib.h2_validate.restype = ci
     lib.h2_gemv.argtypes = [vp, ctypes.c_char, dbl, vp, i64, i64, dbl, vp, i64, vp]
     lib.h2_gemv.restype = ci
+    lib.h2_gemv_ex.argtypes = [vp, ctypes.c_char, dbl, vp, i64, i64, dbl, vp, i64, ci, vp]
+    lib.h2_gemv_ex.restype = ci
+    lib.h2_prepare.argtypes = [vp, ci]
+    lib.h2_prepare.restype = ci
     lib.h2_reserve.argtypes = [vp, i64]
     lib.h2_reserve.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
@@ -77,6 +89,20 @@ def load_library(path: str = LIB_PATH):
     lib.h2_profile.restype = ci
     lib.h2_profile_read.argtypes = [vp, ctypes.POINTER(H2Profile)]
     lib.h2_profile_read.restype = ci
+    lib.h2_batch_load.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t), i64, i64, ci,
+                                  ctypes.POINTER(vp)]
+    lib.h2_batch_load.restype = ci
+    lib.h2_batch_gemv.argtypes = [vp, ctypes.POINTER(H2BatchItem), vp]
+    lib.h2_batch_gemv.restype = ci
+    lib.h2_batch_tune.argtypes = [vp, ctypes.POINTER(H2BatchItem), vp]
+    lib.h2_batch_tune.restype = ci
+    lib.h2_batch_graph.argtypes = [vp, ci]
+    lib.h2_batch_graph.restype = ci
+    lib.h2_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                  ctypes.POINTER(i64)]
+    lib.h2_batch_info.restype = ci
+    lib.h2_batch_free.argtypes = [vp]
+    lib.h2_batch_free.restype = ci
     lib.h2_free.argtypes = [vp]
     lib.h2_free.restype = ci
     lib.h2_last_error.argtypes = []
@@ -143,13 +169,22 @@ class H2Operator:
         _check(load_library().h2_profile_read(self._h, ctypes.byref(p)))
         return p.as_dict()
 
-    def gemv_raw(self, op: str, alpha: float, x_ptr: int, ldx: int, nv: int, beta: float, y_ptr: int,
-                 ldy: int, stream: int = 0):
-        """Direct C-ABI call with device pointers (integers)."""
-        _check(load_library().h2_gemv(self._h, op.encode(), float(alpha), x_ptr or None, ldx, nv, float(beta),
-                                      y_ptr or None, ldy, stream or None))
+    def prepare(self, precision: str):
+        _check(load_library().h2_prepare(self._h, PRECISIONS[precision]))
 
-    def gemv(self, X, op: str = "N", alpha: float = 1.0, beta: float = 0.0, Y=None, stream=None):
+    def gemv_raw(self, op: str, alpha: float, x_ptr: int, ldx: int, nv: int, beta: float, y_ptr: int,
+                 ldy: int, stream: int = 0, precision: str = "fp64"):
+        """Direct C-ABI call with device pointers (integers)."""
+        lib = load_library()
+        if precision == "fp64":
+            _check(lib.h2_gemv(self._h, op.encode(), float(alpha), x_ptr or None, ldx, nv, float(beta),
+                               y_ptr or None, ldy, stream or None))
+        else:
+            _check(lib.h2_gemv_ex(self._h, op.encode(), float(alpha), x_ptr or None, ldx, nv, float(beta),
+                                  y_ptr or None, ldy, PRECISIONS[precision], stream or None))
+
+    def gemv(self, X, op: str = "N", alpha: float = 1.0, beta: float = 0.0, Y=None, stream=None,
+             precision: str = "fp64"):
         """Y <- alpha op(A) X + beta Y.  X, Y: torch tensors (device or host;
         host tensors are copied to the operator's device).  Returns Y."""
         import torch
@@ -175,8 +210,76 @@ class H2Operator:
         ldx = X.stride(1) if nv > 1 else self.n
         ldy = Y.stride(1) if nv > 1 else self.n
         s = stream if stream is not None else torch.cuda.current_stream(dev)
-        self.gemv_raw(op, alpha, X.data_ptr(), ldx, nv, beta, Y.data_ptr(), ldy, s.cuda_stream)
+        self.gemv_raw(op, alpha, X.data_ptr(), ldx, nv, beta, Y.data_ptr(), ldy, s.cuda_stream, precision)
         return Y
 
 
-__all__ = ["H2Operator", "H2Error", "load_library", "validate", "EXPORTS"]
+class H2Batch:
+    """Several operators applied together by merged launches (op 'N', FP64).
+
+    ``bufs``: list of uint8 buffers holding serialized representations.
+    ``gemv(Xs, Ys, nvs, alphas, betas)`` takes per-operator device tensors
+    (column-major n_i x nv_i) and computes Y_i <- alpha_i A_i X_i + beta_i Y_i.
+    """
+
+    def __init__(self, bufs, nv_max: int, device: int = 0):
+        lib = load_library()
+        self._keep = [np.ascontiguousarray(np.asarray(b).view(np.uint8).ravel()) for b in bufs]
+        ptrs = (ctypes.c_void_p * len(bufs))(*[b.ctypes.data for b in self._keep])
+        lens = (ctypes.c_size_t * len(bufs))(*[b.size for b in self._keep])
+        h = ctypes.c_void_p()
+        _check(lib.h2_batch_load(ptrs, lens, len(bufs), nv_max, device, ctypes.byref(h)))
+        self._keep = None  # only read during the load
+        self._h = h
+        self.count = len(bufs)
+        self.nv_max = nv_max
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().h2_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        c, n, l = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        f = ctypes.c_double()
+        _check(load_library().h2_batch_info(self._h, ctypes.byref(c), ctypes.byref(n), ctypes.byref(f),
+                                            ctypes.byref(l)))
+        return {"count": c.value, "total_n": n.value, "flops_per_vector": f.value, "launches": l.value}
+
+    @staticmethod
+    def _items(Xs, Ys, alphas, betas):
+        items = (H2BatchItem * len(Xs))()
+        for i, (X, Y) in enumerate(zip(Xs, Ys)):
+            nv = 0 if Y is None else (Y.shape[1] if Y.dim() > 1 else 1)
+            n = 0 if Y is None else Y.shape[0]
+            items[i] = H2BatchItem(None if X is None else X.data_ptr(), (X.stride(1) if X is not None and nv > 1 else n),
+                                   None if Y is None else Y.data_ptr(), (Y.stride(1) if Y is not None and nv > 1 else n),
+                                   nv, float(alphas[i]), float(betas[i]))
+        return items
+
+    def gemv(self, Xs, Ys, alphas=None, betas=None, stream=None):
+        import torch
+        alphas = alphas if alphas is not None else [1.0] * len(Xs)
+        betas = betas if betas is not None else [0.0] * len(Xs)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(load_library().h2_batch_gemv(self._h, self._items(Xs, Ys, alphas, betas), s.cuda_stream))
+
+    def tune(self, Xs, Ys, alphas=None, betas=None, stream=None):
+        import torch
+        alphas = alphas if alphas is not None else [1.0] * len(Xs)
+        betas = betas if betas is not None else [0.0] * len(Xs)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(load_library().h2_batch_tune(self._h, self._items(Xs, Ys, alphas, betas), s.cuda_stream))
+
+    def graph(self, enable: bool = True):
+        _check(load_library().h2_batch_graph(self._h, 1 if enable else 0))
+
+
+__all__ = ["H2Operator", "H2Batch", "H2Error", "load_library", "validate", "EXPORTS"]

@@ -1,11 +1,12 @@
-// C ABI of libh2gemv: loading (validation, launch schedules built once --
-// the role the paper gives to its per-level marshaling kernels, Algorithm 3,
+// C ABI of libh2gemv: loading (validation; launch plans built once -- the
+// role the paper gives to its per-level marshaling kernels, Algorithm 3,
 // done here at load time because the structure is static), the product
 // h2_gemv, and the helpers declared in include/h2.h.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -26,9 +27,9 @@ int hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? H2_ENOMEM : H2_EHIP;
 }
 
-#define HIP_TRY(expr, what)                       \
-  do {                                            \
-    hipError_t e_ = (expr);                       \
+#define HIP_TRY(expr, what)                          \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
@@ -42,247 +43,292 @@ int upload(const std::vector<T>& v, T** dst, int64_t* bytes) {
   return H2_OK;
 }
 
-// Streaming schedule (op 'N') over block rows: `rows_of` yields, for each
-// output row, its blocks in memory order.
-struct BlockRef {
-  int64_t data;    // element offset of the stored block
-  int64_t in_off;  // input row offset
-  int32_t width;   // columns of the stored block
-};
-
-void add_stream_row(StreamSched& sc, int64_t out_off, int32_t nrows, int64_t out_ld, int64_t in_ld,
-                    const std::vector<BlockRef>& blks) {
+void append_gather(GatherTables& t, const RowSpec& r) {
   RowDesc R{};
-  R.data_off = blks.empty() ? 0 : blks[0].data;
-  R.out_off = out_off;
-  R.nrows = nrows;
-  R.blk_begin = (int32_t)sc.colend.size();
-  int32_t col = 0;
-  for (const BlockRef& b : blks) {
-    col += b.width;
-    sc.colend.push_back(col);
-    sc.in_off.push_back(b.in_off);
+  R.out_off = r.out_off;
+  R.nrows = r.nrows;
+  R.blk_begin = (int32_t)t.data.size();
+  for (const BlockRef& b : r.blks) {
+    t.data.push_back(b.data);
+    t.in_off.push_back(b.in_off);
+    t.mr.push_back(b.mr);
   }
-  R.blk_end = (int32_t)sc.colend.size();
-  R.out_ld = out_ld;
-  R.in_ld = in_ld;
-  sc.rows.push_back(R);
+  R.blk_end = (int32_t)t.data.size();
+  R.out_ld = r.out_ld;
+  R.in_ld = r.in_ld;
+  t.rows.push_back(R);
 }
 
-void add_gather_row(GatherSched& sc, int64_t out_off, int32_t nrows, int64_t out_ld, int64_t in_ld,
-                    const std::vector<BlockRef>& blks, const std::vector<int32_t>& mr) {
-  RowDesc R{};
-  R.out_off = out_off;
-  R.nrows = nrows;
-  R.blk_begin = (int32_t)sc.data.size();
-  for (size_t i = 0; i < blks.size(); ++i) {
-    sc.data.push_back(blks[i].data);
-    sc.in_off.push_back(blks[i].in_off);
-    sc.mr.push_back(mr[i]);
+// Append a phase of streaming rows (narrow rows to the tabled kernel, wide
+// ones to the fallback), longest rows first for load balance.
+void add_stream_phase(h2_op_s* h, std::vector<RowSpec>& rows, int arr, int in, int out, int mode, bool sort,
+                      std::vector<Launch>& dst) {
+  if (sort)
+    std::stable_sort(rows.begin(), rows.end(),
+                     [](const RowSpec& a, const RowSpec& b) { return row_work(a) > row_work(b); });
+  Launch narrow, wide;
+  narrow.kind = KIND_STREAM; wide.kind = KIND_WIDE;
+  narrow.arr = wide.arr = arr;
+  narrow.in = wide.in = in;
+  narrow.out = wide.out = out;
+  narrow.mode = wide.mode = mode;
+  narrow.row_begin = (int64_t)h->rt.rows.size();
+  wide.row_begin = (int64_t)h->wide.rows.size();
+  for (const RowSpec& r : rows) {
+    if ((int64_t)r.blks.size() <= kNbMax) {
+      append_row(h->rt, r);
+      narrow.max_rows = std::max(narrow.max_rows, r.nrows);
+    } else {
+      append_row(h->wide, r);
+      wide.max_rows = std::max(wide.max_rows, r.nrows);
+    }
   }
-  R.blk_end = (int32_t)sc.data.size();
-  R.out_ld = out_ld;
-  R.in_ld = in_ld;
-  sc.rows.push_back(R);
+  narrow.row_count = (int64_t)h->rt.rows.size() - narrow.row_begin;
+  wide.row_count = (int64_t)h->wide.rows.size() - wide.row_begin;
+  if (narrow.row_count) dst.push_back(narrow);
+  if (wide.row_count) dst.push_back(wide);
+}
+
+void add_gather_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int in, int out, std::vector<Launch>& dst) {
+  Launch L;
+  L.kind = KIND_GATHER;
+  L.arr = ARR_MAT;
+  L.in = in;
+  L.out = out;
+  L.mode = MODE_STORE;
+  L.row_begin = (int64_t)h->gt.rows.size();
+  for (const RowSpec& r : rows) append_gather(h->gt, r);
+  L.row_count = (int64_t)h->gt.rows.size() - L.row_begin;
+  if (L.row_count) dst.push_back(L);
 }
 
 void free_device(h2_op_s* h) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
-  F(h->d_mat); F(h->d_perm); F(h->d_lo); F(h->d_m); F(h->d_parent); F(h->d_cptr); F(h->d_hoff);
-  F(h->coupleN.d_rows); F(h->coupleN.d_colend); F(h->coupleN.d_in_off);
-  F(h->denseN.d_rows); F(h->denseN.d_colend); F(h->denseN.d_in_off);
-  F(h->coupleT.d_rows); F(h->coupleT.d_data); F(h->coupleT.d_mr); F(h->coupleT.d_in_off);
-  F(h->denseT.d_rows); F(h->denseT.d_data); F(h->denseT.d_mr); F(h->denseT.d_in_off);
+  F(h->d_mat); F(h->d_trans); F(h->d_perm); F(h->d_pinv); F(h->d_mat32); F(h->d_trans32);
+  F(h->rt.d_rows); F(h->rt.d_colend); F(h->rt.d_in_off);
+  F(h->wide.d_rows); F(h->wide.d_colend); F(h->wide.d_in_off);
+  F(h->gt.d_rows); F(h->gt.d_data); F(h->gt.d_mr); F(h->gt.d_in_off);
   F(h->d_xt); F(h->d_xh); F(h->d_yh); F(h->d_zn);
   for (auto& set : h->ev_pool)
     for (hipEvent_t e : set)
       if (e) (void)hipEventDestroy(e);
   h->ev_pool.clear();
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  h->ev_fork = h->ev_join = nullptr;
+  h->side = nullptr;
 }
 
-// Build schedules, upload; `h` has its device set current.
+// Build plans and upload; the handle's device is current.
 int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
   const int64_t q = P.q, n = P.n;
+  const int64_t* lp = P.level_ptr;
   h->n = n; h->q = q; h->nnodes = P.nnodes; h->nleaves = P.nleaves; h->leaf0 = P.leaf0;
   h->shared = !(P.flags & 1u);
-  // ---- levels, node offsets into the vector trees
   h->lv.resize(q + 1);
-  const int64_t mat0 = P.off_U;  // device matrix array keeps the section layout from U on
   for (int64_t l = 0; l <= q; ++l) {
     LevelInfo& L = h->lv[l];
-    L.begin = P.level_ptr[l];
-    L.count = P.level_ptr[l + 1] - P.level_ptr[l];
+    L.begin = lp[l];
+    L.count = lp[l + 1] - lp[l];
     L.krow = P.krow[l];
     L.kcol = P.kcol[l];
     L.kmax = std::max(L.krow, L.kcol);
-    L.e_off = (P.off_E - mat0) / 8 + P.ebase[l];
-    L.f_off = ((h->shared ? P.off_E : P.off_F) - mat0) / 8 + P.fbase[l];
   }
-  h->u_off = 0;
-  h->v_off = ((h->shared ? P.off_U : P.off_V) - mat0) / 8;
-  h->s_off = (P.off_S - mat0) / 8;
-  h->d_off = (P.off_D - mat0) / 8;
-  std::vector<int64_t> hoff(P.nnodes);
-  int64_t H = 0;
-  for (int64_t l = 0; l <= q; ++l)
-    for (int64_t c = P.level_ptr[l]; c < P.level_ptr[l + 1]; ++c) {
-      hoff[c] = H;
-      H += h->lv[l].kmax;
-    }
+  OpLayout lay;
+  int rc0 = make_layout(P, &lay);
+  if (rc0 != H2_OK) return rc0;
+  const int64_t oU = lay.oU, oE = lay.oE, oV = lay.oV, oF = lay.oF, oS = lay.oS, oD = lay.oD;
+  const int64_t tUT = lay.tUT, tET = lay.tET;
+  const int64_t nU = n * P.krow[q], nE = P.ebase[q + 1], nV = n * P.kcol[q], nF = P.fbase[q + 1];
+  const int64_t ntrans = lay.ntrans;
+  h->n_trans = ntrans;
+  h->n_lowrank = oD;
+  const std::vector<int64_t>& hoff = lay.hoff;
+  const int64_t H = lay.H;
   h->H = H;
-  std::vector<int32_t> perm(n), lo(P.nnodes), msz(P.nnodes), parent(P.nnodes), cptr(P.nnodes + 1, 0);
-  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)P.perm[i];
-  for (int64_t c = 0; c < P.nnodes; ++c) {
-    lo[c] = (int32_t)P.lo[c];
-    msz[c] = (int32_t)(P.hi[c] - P.lo[c]);
-    parent[c] = (int32_t)P.parent[c];
+  auto msz = [&](int64_t c) { return (int32_t)(P.hi[c] - P.lo[c]); };
+
+  // ---- transposed copies of the bases (for the upsweep products)
+  if (ntrans > 0) {
+    std::vector<double> tr(ntrans);
+    build_transposed(buf, lay, tr.data());
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&h->d_trans), ntrans * sizeof(double)), "hipMalloc(trans)");
+    HIP_TRY(hipMemcpy(h->d_trans, tr.data(), ntrans * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy(trans)");
   }
-  // children of p are consecutive: cptr[p] = first child, cptr[p+1] = one past the last
+
+  // ---- plan for op 'N': rows from the shared emitter (column-major layout)
   {
-    int64_t next_child = 1;
-    for (int64_t p = 0; p < P.nnodes; ++p) {
-      cptr[p] = (int32_t)next_child;
-      while (next_child < P.nnodes && P.parent[next_child] == p) ++next_child;
+    RowsN R;
+    RowBases B;
+    B.ld_x = n;
+    B.ld_h = H;
+    emit_rows_N(lay, B, &R);
+    Plan& plan = h->planN;
+    add_stream_phase(h, R.up[0], ARR_TRANS, BUF_XT, BUF_XH, MODE_STORE, false, plan.up);
+    for (int64_t hh = 1; hh <= q; ++hh) add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
+    add_stream_phase(h, R.couple, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple);
+    for (int64_t l = 1; l <= q; ++l) add_stream_phase(h, R.down[l - 1], ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
+    add_stream_phase(h, R.dense, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, true, plan.dense);
+    for (Launch& L : plan.dense) L.lowrank = false;
+    std::vector<Launch> outl;
+    add_stream_phase(h, R.out, ARR_MAT, BUF_YH, BUF_ZN, MODE_FINAL, false, outl);
+    if (outl.size() != 1) {
+      set_error("internal: leaf expansion schedule");
+      return H2_EUNSUPPORTED;
     }
-    cptr[P.nnodes] = (int32_t)next_child;
+    plan.out = outl[0];
   }
-  // ---- coupling schedules: op 'N' rows (CSR), op 'T' columns (CSC)
-  int64_t csp = 0, csp_dense = 0;
+  // ---- plan for op 'T' (A^T = D^T + V S^T U^T): upsweep with U, E; coupling
+  // and dense blocks read transposed; downsweep with V, F
   {
-    std::vector<BlockRef> blks;
-    std::vector<std::vector<int64_t>> by_col;  // per node of the level: global block ids
+    const int64_t* lp = P.level_ptr;
+    Plan& plan = h->planT;
+    const int64_t* kc = P.krow;  // ranks of the input side
+    const int64_t* kr = P.kcol;  // ranks of the output side
+    std::vector<RowSpec> rows;
+    for (int64_t t = P.leaf0; t < P.nnodes; ++t)
+      rows.push_back({tUT + P.lo[t] * kc[q], hoff[t], H, n, (int32_t)kc[q], {BlockRef{0, P.lo[t], msz(t), 0}}});
+    add_stream_phase(h, rows, ARR_TRANS, BUF_XT, BUF_XH, MODE_STORE, false, plan.up);
+    for (int64_t l = q; l >= 1; --l) {
+      rows.clear();
+      for (int64_t p = lp[l - 1]; p < lp[l]; ++p) {
+        RowSpec r{tET + lay.eoff(lay.cbeg[p], l), hoff[p], H, H, (int32_t)kc[l - 1], {}};
+        for (int64_t c = lay.cbeg[p]; c < lay.cbeg[p + 1]; ++c) r.blks.push_back({0, hoff[c], (int32_t)kc[l], 0});
+        rows.push_back(r);
+      }
+      add_stream_phase(h, rows, ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
+    }
+    rows.clear();
     for (int64_t l = 0; l <= q; ++l) {
-      const LevelInfo& L = h->lv[l];
       const int64_t* rp = P.s_rowptr + P.rp_base[l];
-      const int64_t bsz = L.krow * L.kcol;
-      by_col.assign(L.count, {});
-      for (int64_t t = 0; t < L.count; ++t) {
-        blks.clear();
-        for (int64_t b = rp[t]; b < rp[t + 1]; ++b) {
-          const int64_t g = P.blk_base[l] + b, s = P.s_col[g];
-          blks.push_back({h->s_off + P.sdat[l] + b * bsz, hoff[L.begin + s], (int32_t)L.kcol});
-          by_col[s].push_back(b);
-        }
-        csp = std::max<int64_t>(csp, (int64_t)blks.size());
-        add_stream_row(h->coupleN, hoff[L.begin + t], (int32_t)L.krow, H, H, blks);
-      }
-      // op 'T': output node s gets sum_t S_ts^T x^_t
-      std::vector<int32_t> mr;
-      for (int64_t s = 0; s < L.count; ++s) {
-        blks.clear();
-        mr.clear();
-        // row node of block b: search the CSR (b is increasing with t)
-        for (int64_t b : by_col[s]) {
-          const int64_t t = std::upper_bound(rp, rp + L.count + 1, b) - rp - 1;
-          blks.push_back({h->s_off + P.sdat[l] + b * bsz, hoff[L.begin + t], (int32_t)L.kcol});
-          mr.push_back((int32_t)L.krow);
-        }
-        csp = std::max<int64_t>(csp, (int64_t)blks.size());
-        add_gather_row(h->coupleT, hoff[L.begin + s], (int32_t)L.kcol, H, H, blks, mr);
-      }
+      const int64_t nl = lp[l + 1] - lp[l], bsz = P.krow[l] * P.kcol[l];
+      std::vector<std::vector<BlockRef>> by_col(nl);
+      for (int64_t t = 0; t < nl; ++t)
+        for (int64_t b = rp[t]; b < rp[t + 1]; ++b)
+          by_col[P.s_col[P.blk_base[l] + b]].push_back({oS + P.sdat[l] + b * bsz, hoff[lp[l] + t], 0, (int32_t)P.krow[l]});
+      for (int64_t s = 0; s < nl; ++s)
+        rows.push_back({0, hoff[lp[l] + s], H, H, (int32_t)P.kcol[l], std::move(by_col[s])});
     }
+    add_gather_phase(h, rows, BUF_XH, BUF_YH, plan.couple);
+    for (int64_t l = 1; l <= q; ++l) {
+      rows.clear();
+      for (int64_t c = lp[l]; c < lp[l + 1]; ++c)
+        rows.push_back({oF + lay.foff(c, l), hoff[c], H, H, (int32_t)kr[l],
+                        {BlockRef{0, hoff[P.parent[c]], (int32_t)kr[l - 1], 0}}});
+      add_stream_phase(h, rows, ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
+    }
+    rows.clear();
+    std::vector<std::vector<BlockRef>> by_col(P.nleaves);
+    for (int64_t t = 0; t < P.nleaves; ++t)
+      for (int64_t b = P.d_rowptr[t]; b < P.d_rowptr[t + 1]; ++b)
+        by_col[P.d_col[b]].push_back({oD + P.ddat[b], P.lo[P.leaf0 + t], 0, msz(P.leaf0 + t)});
+    for (int64_t s = 0; s < P.nleaves; ++s)
+      rows.push_back({0, P.lo[P.leaf0 + s], n, n, msz(P.leaf0 + s), std::move(by_col[s])});
+    add_gather_phase(h, rows, BUF_XT, BUF_ZN, plan.dense);
+    for (Launch& L : plan.dense) L.lowrank = false;
+    rows.clear();
+    for (int64_t t = P.leaf0; t < P.nnodes; ++t)
+      rows.push_back({oV + P.lo[t] * kr[q], P.lo[t], n, H, msz(t), {BlockRef{0, hoff[t], (int32_t)kr[q], 0}}});
+    std::vector<Launch> outl;
+    add_stream_phase(h, rows, ARR_MAT, BUF_YH, BUF_ZN, MODE_FINAL, false, outl);
+    if (outl.size() != 1) {
+      set_error("internal: leaf expansion schedule");
+      return H2_EUNSUPPORTED;
+    }
+    plan.out = outl[0];
   }
-  // ---- dense schedules over leaves
-  {
-    std::vector<BlockRef> blks;
-    std::vector<std::vector<int64_t>> by_col(P.nleaves);
-    for (int64_t t = 0; t < P.nleaves; ++t) {
-      blks.clear();
-      for (int64_t b = P.d_rowptr[t]; b < P.d_rowptr[t + 1]; ++b) {
-        const int64_t s = P.d_col[b];
-        blks.push_back({h->d_off + P.ddat[b], P.lo[P.leaf0 + s], (int32_t)(P.hi[P.leaf0 + s] - P.lo[P.leaf0 + s])});
-        by_col[s].push_back(b);
-      }
-      csp_dense = std::max<int64_t>(csp_dense, (int64_t)blks.size());
-      add_stream_row(h->denseN, P.lo[P.leaf0 + t], msz[P.leaf0 + t], n, n, blks);
-    }
-    std::vector<int32_t> mr;
-    for (int64_t s = 0; s < P.nleaves; ++s) {
-      blks.clear();
-      mr.clear();
-      for (int64_t b : by_col[s]) {
-        const int64_t t = std::upper_bound(P.d_rowptr, P.d_rowptr + P.nleaves + 1, b) - P.d_rowptr - 1;
-        blks.push_back({h->d_off + P.ddat[b], P.lo[P.leaf0 + t], msz[P.leaf0 + s]});
-        mr.push_back(msz[P.leaf0 + t]);
-      }
-      csp_dense = std::max<int64_t>(csp_dense, (int64_t)blks.size());
-      add_gather_row(h->denseT, P.lo[P.leaf0 + s], msz[P.leaf0 + s], n, n, blks, mr);
-    }
-  }
+  (void)oU; (void)oE;
+
   // ---- stats
+  int64_t csp = 0, csp_dense = 0;
+  for (int64_t l = 0; l <= q; ++l) {
+    const int64_t* rp = P.s_rowptr + P.rp_base[l];
+    const int64_t nl = lp[l + 1] - lp[l];
+    std::vector<int64_t> colcnt(nl, 0);
+    for (int64_t t = 0; t < nl; ++t) {
+      csp = std::max(csp, rp[t + 1] - rp[t]);
+      for (int64_t b = rp[t]; b < rp[t + 1]; ++b) ++colcnt[P.s_col[P.blk_base[l] + b]];
+    }
+    for (int64_t c : colcnt) csp = std::max(csp, c);
+  }
+  {
+    std::vector<int64_t> colcnt(P.nleaves, 0);
+    for (int64_t t = 0; t < P.nleaves; ++t) {
+      csp_dense = std::max(csp_dense, P.d_rowptr[t + 1] - P.d_rowptr[t]);
+      for (int64_t b = P.d_rowptr[t]; b < P.d_rowptr[t + 1]; ++b) ++colcnt[P.d_col[b]];
+    }
+    for (int64_t c : colcnt) csp_dense = std::max(csp_dense, c);
+  }
   h2_stats_t& st = h->stats;
   st = h2_stats_t{};
   st.n = n; st.depth = q; st.nnodes = P.nnodes; st.nleaves = P.nleaves;
   st.ncoupling = P.nadm_tot; st.ndense = P.ndense; st.csp = csp; st.csp_dense = csp_dense;
-  st.entries_U = n * P.krow[q];
-  st.entries_V = n * P.kcol[q];
-  st.entries_E = P.ebase[q + 1];
-  st.entries_F = P.fbase[q + 1];
+  st.entries_U = nU; st.entries_V = nV; st.entries_E = nE; st.entries_F = nF;
   st.entries_S = P.sdat[q + 1];
   st.entries_D = P.ddat[P.ndense];
-  int64_t tree_rows = 0;
-  for (int64_t l = 0; l <= q; ++l) tree_rows += h->lv[l].count * h->lv[l].kmax;
-  st.tree_rows = tree_rows;
+  for (int64_t l = 0; l <= q; ++l) st.tree_rows += h->lv[l].count * h->lv[l].kmax;
   st.shared_basis = h->shared ? 1 : 0;
   for (int64_t l = 0; l <= q; ++l) st.max_rank = std::max(st.max_rank, h->lv[l].kmax);
-  for (int64_t t = P.leaf0; t < P.nnodes; ++t) st.max_leaf = std::max<int64_t>(st.max_leaf, msz[t]);
+  for (int64_t t = P.leaf0; t < P.nnodes; ++t) st.max_leaf = std::max<int64_t>(st.max_leaf, msz(t));
+
   // ---- upload
   const int64_t mat_bytes = P.off_end - P.off_U;
   if (mat_bytes > 0) {
     HIP_TRY(hipMalloc(reinterpret_cast<void**>(&h->d_mat), mat_bytes), "hipMalloc(matrix data)");
     HIP_TRY(hipMemcpy(h->d_mat, buf + P.off_U, mat_bytes, hipMemcpyHostToDevice), "hipMemcpy(matrix data)");
   }
+  std::vector<int32_t> perm(n), pinv(n);
+  for (int64_t i = 0; i < n; ++i) {
+    perm[i] = (int32_t)P.perm[i];
+    pinv[P.perm[i]] = (int32_t)i;
+  }
+  for (const auto* v : {&h->planN.up, &h->planN.couple, &h->planN.down, &h->planN.dense})
+    for (const Launch& L : *v)
+      if (L.kind != KIND_STREAM) h->mfma_ok = false;
   int64_t ib = 0;
   int rc;
-  std::vector<int64_t> hoff64(hoff);
-  if ((rc = upload(perm, &h->d_perm, &ib)) || (rc = upload(lo, &h->d_lo, &ib)) || (rc = upload(msz, &h->d_m, &ib)) ||
-      (rc = upload(parent, &h->d_parent, &ib)) || (rc = upload(cptr, &h->d_cptr, &ib)) ||
-      (rc = upload(hoff64, &h->d_hoff, &ib)) ||
-      (rc = upload(h->coupleN.rows, &h->coupleN.d_rows, &ib)) ||
-      (rc = upload(h->coupleN.colend, &h->coupleN.d_colend, &ib)) ||
-      (rc = upload(h->coupleN.in_off, &h->coupleN.d_in_off, &ib)) ||
-      (rc = upload(h->denseN.rows, &h->denseN.d_rows, &ib)) ||
-      (rc = upload(h->denseN.colend, &h->denseN.d_colend, &ib)) ||
-      (rc = upload(h->denseN.in_off, &h->denseN.d_in_off, &ib)) ||
-      (rc = upload(h->coupleT.rows, &h->coupleT.d_rows, &ib)) ||
-      (rc = upload(h->coupleT.data, &h->coupleT.d_data, &ib)) ||
-      (rc = upload(h->coupleT.mr, &h->coupleT.d_mr, &ib)) ||
-      (rc = upload(h->coupleT.in_off, &h->coupleT.d_in_off, &ib)) ||
-      (rc = upload(h->denseT.rows, &h->denseT.d_rows, &ib)) ||
-      (rc = upload(h->denseT.data, &h->denseT.d_data, &ib)) ||
-      (rc = upload(h->denseT.mr, &h->denseT.d_mr, &ib)) ||
-      (rc = upload(h->denseT.in_off, &h->denseT.d_in_off, &ib)))
+  if ((rc = upload(perm, &h->d_perm, &ib)) || (rc = upload(pinv, &h->d_pinv, &ib)) || (rc = upload(h->rt.rows, &h->rt.d_rows, &ib)) ||
+      (rc = upload(h->rt.colend, &h->rt.d_colend, &ib)) || (rc = upload(h->rt.in_off, &h->rt.d_in_off, &ib)) ||
+      (rc = upload(h->wide.rows, &h->wide.d_rows, &ib)) ||
+      (rc = upload(h->wide.colend, &h->wide.d_colend, &ib)) ||
+      (rc = upload(h->wide.in_off, &h->wide.d_in_off, &ib)) || (rc = upload(h->gt.rows, &h->gt.d_rows, &ib)) ||
+      (rc = upload(h->gt.data, &h->gt.d_data, &ib)) || (rc = upload(h->gt.mr, &h->gt.d_mr, &ib)) ||
+      (rc = upload(h->gt.in_off, &h->gt.d_in_off, &ib)))
     return rc;
   h->index_bytes = ib;
-  h->stats.device_bytes = mat_bytes + ib;
+  HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "hipStreamCreate");
+  HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming), "hipEventCreate");
+  HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming), "hipEventCreate");
+  h->stats.device_bytes = mat_bytes + ntrans * (int64_t)sizeof(double) + ib;
   return H2_OK;
 }
 
 int ensure_workspace(h2_op_s* h, int64_t nv) {
-  const int64_t want = std::min<int64_t>(std::max<int64_t>(nv, 1), kNvChunk);
-  if (want <= h->cap) return H2_OK;
+  const int64_t want = (nv > kPassVectors && h->mfma_ok) ? kPassVectorsMfma : kPassVectors;
+  if (h->cap >= want) return H2_OK;
+  const int64_t Hs = std::max<int64_t>(h->H, 1);
+  if (h->cap > 0) {  // grow: the old buffers may still be in use by queued work
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(workspace growth)");
+    (void)hipFree(h->d_xt); (void)hipFree(h->d_xh); (void)hipFree(h->d_yh); (void)hipFree(h->d_zn);
+    h->d_xt = h->d_xh = h->d_yh = h->d_zn = nullptr;
+    h->stats.device_bytes -= (int64_t)sizeof(double) * (2 * h->n + 2 * Hs) * h->cap;
+    h->cap = 0;
+  }
   double *xt = nullptr, *xh = nullptr, *yh = nullptr, *zn = nullptr;
-  auto cleanup = [&]() {
+  hipError_t e;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&xt), sizeof(double) * h->n * want)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&xh), sizeof(double) * Hs * want)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&yh), sizeof(double) * Hs * want)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&zn), sizeof(double) * h->n * want)) != hipSuccess) {
     if (xt) (void)hipFree(xt);
     if (xh) (void)hipFree(xh);
     if (yh) (void)hipFree(yh);
     if (zn) (void)hipFree(zn);
-  };
-  hipError_t e;
-  if ((e = hipMalloc(reinterpret_cast<void**>(&xt), sizeof(double) * h->n * want)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&xh), sizeof(double) * std::max<int64_t>(h->H, 1) * want)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&yh), sizeof(double) * std::max<int64_t>(h->H, 1) * want)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&zn), sizeof(double) * h->n * want)) != hipSuccess) {
-    cleanup();
     return hip_fail(e, "hipMalloc(workspace)");
   }
-  // the old workspace may still be in use by queued work
-  if (h->cap > 0) {
-    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(workspace growth)");
-    (void)hipFree(h->d_xt); (void)hipFree(h->d_xh); (void)hipFree(h->d_yh); (void)hipFree(h->d_zn);
-  }
   h->d_xt = xt; h->d_xh = xh; h->d_yh = yh; h->d_zn = zn;
-  h->stats.device_bytes += (int64_t)sizeof(double) * (2 * h->n + 2 * std::max<int64_t>(h->H, 1)) * (want - h->cap);
+  h->stats.device_bytes += (int64_t)sizeof(double) * (2 * h->n + 2 * Hs) * want;
   h->cap = want;
   return H2_OK;
 }
@@ -312,7 +358,12 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out) {
   h2_op_s* h = new (std::nothrow) h2_op_s();
   if (!h) { set_error("out of host memory"); return H2_ENOMEM; }
   h->device = device;
-  rc = build_handle(buf, P, h);
+  try {
+    rc = build_handle(buf, P, h);
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory while building schedules");
+    rc = H2_ENOMEM;
+  }
   if (rc != H2_OK) {
     free_device(h);
     delete h;
@@ -322,55 +373,109 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out) {
   return H2_OK;
 }
 
-// One pass of the product over nv <= cap vectors (X, Y already offset).
+// nvp > 0: MFMA path with nvp vectors per row (row-major workspace).
+// f32: the low-rank launches read the FP32 copy (the dense phase never does).
+int run_launch(h2_op_s* h, const Launch& L, int nv, const Epilogue& ep, hipStream_t s, int nvp = 0,
+               int mode_override = -1, bool f32 = false) {
+  double* bufs[4] = {h->d_xt, h->d_xh, h->d_yh, h->d_zn};
+  const bool lowp = f32 && L.lowrank && L.kind != KIND_WIDE;
+  const double* data = L.arr == ARR_TRANS ? h->d_trans : h->d_mat;
+  const float* data32 = L.arr == ARR_TRANS ? h->d_trans32 : h->d_mat32;
+  double* out = bufs[mode_override >= 0 ? BUF_ZN : L.out];
+  const int mode = mode_override >= 0 ? mode_override : L.mode;
+  hipError_t e = hipSuccess;
+  if (nvp > 0) {
+    e = lowp ? launch_rows_mfma<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s)
+             : launch_rows_mfma<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s);
+  } else if (L.kind == KIND_STREAM) {
+    e = lowp ? launch_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off, data32,
+                                  bufs[L.in], out, nv, mode, ep, s)
+             : launch_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off, data,
+                                   bufs[L.in], out, nv, mode, ep, s);
+  } else if (L.kind == KIND_WIDE) {
+    e = launch_rows_wide(h->wide.d_rows + L.row_begin, L.row_count, h->wide.d_colend, h->wide.d_in_off, data,
+                         bufs[L.in], out, nv, s);
+  } else {
+    e = lowp ? launch_gather<float>(h->gt.d_rows + L.row_begin, L.row_count, h->gt.d_data, h->gt.d_mr,
+                                    h->gt.d_in_off, data32, bufs[L.in], out, nv, s)
+             : launch_gather<double>(h->gt.d_rows + L.row_begin, L.row_count, h->gt.d_data, h->gt.d_mr,
+                                     h->gt.d_in_off, data, bufs[L.in], out, nv, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return H2_OK;
+}
+
+int prepare_f32(h2_op_s* h) {
+  if (h->d_mat32 || h->n_lowrank + h->n_trans == 0) return H2_OK;
+  float *m32 = nullptr, *t32 = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&m32), sizeof(float) * std::max<int64_t>(h->n_lowrank, 1))) !=
+          hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&t32), sizeof(float) * std::max<int64_t>(h->n_trans, 1))) !=
+          hipSuccess) {
+    if (m32) (void)hipFree(m32);
+    return hip_fail(e, "hipMalloc(FP32 copy)");
+  }
+  h->d_mat32 = m32;
+  h->d_trans32 = t32;
+  HIP_TRY(launch_to_f32(h->d_mat, m32, h->n_lowrank, nullptr), "FP32 copy");
+  HIP_TRY(launch_to_f32(h->d_trans, t32, h->n_trans, nullptr), "FP32 copy");
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(FP32 copy)");
+  h->stats.device_bytes += (int64_t)sizeof(float) * (h->n_lowrank + h->n_trans);
+  return H2_OK;
+}
+
+// One pass of the product: nv <= kPassVectors vectors on the streaming path
+// (nvp == 0), or nv <= kPassVectorsMfma vectors padded to nvp on the MFMA path.
 int gemv_pass(h2_op_s* h, bool trans, double alpha, const double* X, int64_t ldx, int nv, double beta, double* Y,
-              int64_t ldy, hipStream_t s) {
-  const int64_t q = h->q, n = h->n, H = h->H;
-  std::array<hipEvent_t, 7>* ev = nullptr;
+              int64_t ldy, hipStream_t s, int nvp, bool f32) {
+  const Plan& plan = trans ? h->planT : h->planN;
+  std::array<hipEvent_t, 9>* ev = nullptr;
   if (h->profiling) {
     if (h->ev_used == h->ev_pool.size()) {
-      std::array<hipEvent_t, 7> set{};
+      std::array<hipEvent_t, 9> set{};
       for (auto& e : set) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
       h->ev_pool.push_back(set);
     }
     ev = &h->ev_pool[h->ev_used++];
   }
-  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord((*ev)[i], s) : hipSuccess; };
-  const double* mat = h->d_mat;
-  // the operator's column basis (input side) and row basis (output side)
-  const double* Bcol = mat + (trans ? h->u_off : h->v_off);
-  const double* Brow = mat + (trans ? h->v_off : h->u_off);
-  auto Tcol = [&](int64_t l) { return mat + (trans ? h->lv[l].e_off : h->lv[l].f_off); };
-  auto Trow = [&](int64_t l) { return mat + (trans ? h->lv[l].f_off : h->lv[l].e_off); };
-  auto kcol = [&](int64_t l) { return (int)(trans ? h->lv[l].krow : h->lv[l].kcol); };
-  auto krow = [&](int64_t l) { return (int)(trans ? h->lv[l].kcol : h->lv[l].krow); };
-
-  HIP_TRY(mark(0), "hipEventRecord");
-  HIP_TRY(launch_permute_in(X, ldx, h->d_perm, h->d_xt, n, nv, s), "permute");
-  HIP_TRY(mark(1), "hipEventRecord");
-  HIP_TRY(launch_leaf_up(Bcol, kcol(q), h->leaf0, h->nleaves, h->d_lo, h->d_m, h->d_hoff, h->d_xt, n, h->d_xh, H,
-                         nv, s), "leaf upsweep");
-  for (int64_t l = q; l >= 1; --l)
-    HIP_TRY(launch_transfer_up(Tcol(l), kcol(l), kcol(l - 1), h->lv[l - 1].begin, h->lv[l - 1].count,
-                               h->lv[l].begin, h->d_cptr, h->d_hoff, h->d_xh, H, nv, s), "transfer upsweep");
-  HIP_TRY(mark(2), "hipEventRecord");
-  if (!trans)
-    HIP_TRY(launch_stream_rows(h->coupleN, mat, h->d_xh, h->d_yh, nv, s), "coupling");
-  else
-    HIP_TRY(launch_gather_rows(h->coupleT, mat, h->d_xh, h->d_yh, nv, s), "coupling");
-  HIP_TRY(mark(3), "hipEventRecord");
-  for (int64_t l = 1; l <= q; ++l)
-    HIP_TRY(launch_transfer_down(Trow(l), krow(l), krow(l - 1), h->lv[l].begin, h->lv[l].count, h->d_parent,
-                                 h->d_hoff, h->d_yh, H, nv, s), "transfer downsweep");
-  HIP_TRY(mark(4), "hipEventRecord");
-  if (!trans)
-    HIP_TRY(launch_stream_rows(h->denseN, mat, h->d_xt, h->d_zn, nv, s), "dense");
-  else
-    HIP_TRY(launch_gather_rows(h->denseT, mat, h->d_xt, h->d_zn, nv, s), "dense");
-  HIP_TRY(mark(5), "hipEventRecord");
-  HIP_TRY(launch_leaf_down(Brow, krow(q), h->leaf0, h->nleaves, h->d_lo, h->d_m, h->d_hoff, h->d_yh, H, h->d_zn, n,
-                           h->d_perm, alpha, beta, Y, ldy, nv, s), "leaf expansion");
-  HIP_TRY(mark(6), "hipEventRecord");
+  auto mark = [&](int i, hipStream_t st) -> int {
+    if (ev) HIP_TRY(hipEventRecord((*ev)[i], st), "hipEventRecord");
+    return H2_OK;
+  };
+  Epilogue ep{h->d_zn, h->d_perm, alpha, beta, Y, ldy, h->n};
+  int rc;
+#define STEP(x) do { if ((rc = (x)) != H2_OK) return rc; } while (0)
+  STEP(mark(0, s));
+  if (nvp) HIP_TRY(launch_permute_in_rm(X, ldx, h->d_pinv, h->d_xt, h->n, nv, nvp, s), "permute");
+  else HIP_TRY(launch_permute_in(X, ldx, h->d_perm, h->d_xt, h->n, nv, s), "permute");
+  STEP(mark(1, s));
+  // dense near field on the side stream, concurrent with the low-rank phases
+  HIP_TRY(hipEventRecord(h->ev_fork, s), "hipEventRecord(fork)");
+  HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0), "hipStreamWaitEvent(fork)");
+  STEP(mark(5, h->side));
+  for (const Launch& L : plan.dense) STEP(run_launch(h, L, nv, ep, h->side, nvp));
+  STEP(mark(6, h->side));
+  HIP_TRY(hipEventRecord(h->ev_join, h->side), "hipEventRecord(join)");
+  for (const Launch& L : plan.up) STEP(run_launch(h, L, nv, ep, s, nvp, -1, f32));
+  STEP(mark(2, s));
+  for (const Launch& L : plan.couple) STEP(run_launch(h, L, nv, ep, s, nvp, -1, f32));
+  STEP(mark(3, s));
+  for (const Launch& L : plan.down) STEP(run_launch(h, L, nv, ep, s, nvp, -1, f32));
+  STEP(mark(4, s));
+  HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0), "hipStreamWaitEvent(join)");
+  STEP(mark(7, s));
+  if (nvp) {
+    // Z += U y^ (into the dense partial), then Y = alpha Z[pinv] + beta Y
+    STEP(run_launch(h, plan.out, nv, ep, s, nvp, MODE_ACCUM, f32));
+    HIP_TRY(launch_permute_out_rm(h->d_zn, h->d_pinv, alpha, beta, Y, ldy, h->n, nv, nvp, s), "permute out");
+  } else {
+    STEP(run_launch(h, plan.out, nv, ep, s, 0, -1, f32));
+  }
+  STEP(mark(8, s));
+#undef STEP
   return H2_OK;
 }
 
@@ -401,8 +506,14 @@ int h2_load(const char* path, int device, h2_handle* out) {
   const long long len = std::ftell(f);
   std::fseek(f, 0, SEEK_SET);
   if (len < 0) { std::fclose(f); set_error("cannot size file"); return H2_EIO; }
-  // 64-byte aligned host copy
-  std::vector<uint64_t> storage(((size_t)len + 7) / 8);
+  std::vector<uint64_t> storage;
+  try {
+    storage.resize(((size_t)len + 7) / 8);
+  } catch (const std::bad_alloc&) {
+    std::fclose(f);
+    set_error("out of host memory");
+    return H2_ENOMEM;
+  }
   const size_t got = std::fread(storage.data(), 1, (size_t)len, f);
   std::fclose(f);
   if (got != (size_t)len) { set_error("short read"); return H2_EIO; }
@@ -416,9 +527,10 @@ int h2_reserve(h2_handle h, int64_t nv_max) {
   return ensure_workspace(h, nv_max);
 }
 
-int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double beta, double* Y,
-            int64_t ldy, void* stream) {
+int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double beta,
+               double* Y, int64_t ldy, int prec, void* stream) {
   if (!h) { set_error("null handle"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32) { set_error("unknown precision"); return H2_EINVAL; }
   const bool trans = op == 'T' || op == 't';
   if (!trans && op != 'N' && op != 'n') { set_error("op must be 'N' or 'T'"); return H2_EINVAL; }
   if (nv < 0) { set_error("nv < 0"); return H2_EINVAL; }
@@ -441,13 +553,33 @@ int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, in
   }
   int rc = ensure_workspace(h, nv);
   if (rc != H2_OK) return rc;
-  for (int64_t v0 = 0; v0 < nv; v0 += h->cap) {
-    const int nvc = (int)std::min<int64_t>(h->cap, nv - v0);
-    rc = gemv_pass(h, trans, alpha, X + ldx * v0, ldx, nvc, beta, Y + ldy * v0, ldy, s);
+  const bool f32 = prec == H2_PREC_FP32;
+  if (f32 && (rc = prepare_f32(h)) != H2_OK) return rc;
+  // multi-vector products of op 'N' go to the MFMA kernels
+  const bool mfma = !trans && nv > kPassVectors && h->mfma_ok && h->cap >= kPassVectorsMfma;
+  const int64_t pass = mfma ? kPassVectorsMfma : kPassVectors;
+  for (int64_t v0 = 0; v0 < nv; v0 += pass) {
+    const int nvc = (int)std::min<int64_t>(pass, nv - v0);
+    rc = gemv_pass(h, trans, alpha, X + ldx * v0, ldx, nvc, beta, Y + ldy * v0, ldy, s,
+                   mfma ? (nvc + 15) / 16 * 16 : 0, f32);
     if (rc != H2_OK) return rc;
   }
   if (h->profiling) ++h->prof.calls;
   return H2_OK;
+}
+
+int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double beta, double* Y,
+            int64_t ldy, void* stream) {
+  return h2_gemv_ex(h, op, alpha, X, ldx, nv, beta, Y, ldy, H2_PREC_FP64, stream);
+}
+
+int h2_prepare(h2_handle h, int prec) {
+  if (!h) { set_error("null handle"); return H2_EINVAL; }
+  if (prec == H2_PREC_FP64) return H2_OK;
+  if (prec != H2_PREC_FP32) { set_error("unknown precision"); return H2_EINVAL; }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  return prepare_f32(h);
 }
 
 int h2_stats(h2_handle h, h2_stats_t* st) {
@@ -473,18 +605,18 @@ int h2_profile_read(h2_handle h, h2_profile_t* out) {
   DeviceGuard guard(h->device);
   for (size_t i = 0; i < h->ev_used; ++i) {
     auto& e = h->ev_pool[i];
+    HIP_TRY(hipEventSynchronize(e[8]), "hipEventSynchronize");
     HIP_TRY(hipEventSynchronize(e[6]), "hipEventSynchronize");
-    float t[6];
-    for (int k = 0; k < 6; ++k) HIP_TRY(hipEventElapsedTime(&t[k], e[k], e[k + 1]), "hipEventElapsedTime");
-    float tot;
-    HIP_TRY(hipEventElapsedTime(&tot, e[0], e[6]), "hipEventElapsedTime");
+    float t[9];
+    const int from[7] = {0, 1, 2, 3, 5, 7, 0}, to[7] = {1, 2, 3, 4, 6, 8, 8};
+    for (int k = 0; k < 7; ++k) HIP_TRY(hipEventElapsedTime(&t[k], e[from[k]], e[to[k]]), "hipEventElapsedTime");
     h->prof.ms_permute += t[0];
     h->prof.ms_upsweep += t[1];
     h->prof.ms_coupling += t[2];
     h->prof.ms_downsweep += t[3];
     h->prof.ms_dense += t[4];
     h->prof.ms_leaf_out += t[5];
-    h->prof.ms_total += tot;
+    h->prof.ms_total += t[6];
   }
   h->ev_used = 0;
   *out = h->prof;

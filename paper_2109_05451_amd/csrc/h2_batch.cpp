@@ -1,0 +1,434 @@
+// Cross-operator batching: several H^2 operators in one device arena, all
+// applied by one sequence of merged launches (declarations in include/h2.h).
+//
+// Every operator contributes the rows of each op-'N' phase (h2_plan.cpp)
+// with its own arena offsets, so rows of different operators mix freely in
+// one launch.  Uneven trees are merged level by level: upsweep launch h holds
+// transfer level q_i - h + 1 of every operator with q_i >= h (aligned by
+// height from the leaves), downsweep launch l holds level l of every operator
+// with q_i >= l (aligned by depth from the root).
+#include <algorithm>
+#include <array>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "h2_internal.h"
+
+namespace h2 {
+namespace {
+
+int hip_fail_b(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? H2_ENOMEM : H2_EHIP;
+}
+
+#define HIP_TRYB(expr, what)                            \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail_b(e_, what);  \
+  } while (0)
+
+struct DevGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+}  // namespace h2
+
+struct h2_batch_s {
+  int device = 0;
+  int64_t count = 0, nvp = 16, nv_max = 1, nmax = 0, total_n = 0;
+  double flops_per_vector = 0.0;
+  std::vector<int64_t> n, pinv_off, xt_row, zn_row;
+  double* d_mat = nullptr;
+  double* d_trans = nullptr;
+  double* d_ws = nullptr;
+  int32_t* d_pinv = nullptr;
+  h2::RowTables rt;
+  std::vector<h2::Launch> up, couple, down, dense, out;
+  h2::BatchItem* h_items = nullptr;  // pinned
+  h2::BatchItem* d_items = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_items = nullptr;
+  bool items_pending = false;
+  bool use_graph = false;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+namespace h2 {
+namespace {
+
+void free_batch(h2_batch_s* b) {
+  auto F = [](void* p) { if (p) (void)hipFree(p); };
+  F(b->d_mat); F(b->d_trans); F(b->d_ws); F(b->d_pinv); F(b->d_items);
+  F(b->rt.d_rows); F(b->rt.d_colend); F(b->rt.d_in_off);
+  if (b->h_items) (void)hipHostFree(b->h_items);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->ev_items) (void)hipEventDestroy(b->ev_items);
+  if (b->side) (void)hipStreamDestroy(b->side);
+}
+
+void add_phase(h2_batch_s* b, std::vector<RowSpec>& rows, int arr, int mode, bool sort, bool lowrank,
+               std::vector<Launch>& dst) {
+  if (rows.empty()) return;
+  if (sort)
+    std::stable_sort(rows.begin(), rows.end(),
+                     [](const RowSpec& x, const RowSpec& y) { return row_work(x) > row_work(y); });
+  Launch L;
+  L.kind = KIND_STREAM;
+  L.arr = arr;
+  L.mode = mode;
+  L.lowrank = lowrank;
+  L.row_begin = (int64_t)b->rt.rows.size();
+  for (const RowSpec& r : rows) {
+    append_row(b->rt, r);
+    L.max_rows = std::max(L.max_rows, r.nrows);
+  }
+  L.row_count = (int64_t)b->rt.rows.size() - L.row_begin;
+  dst.push_back(L);
+}
+
+int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_batch_s* b) {
+  std::vector<Parsed> P(count);
+  std::vector<OpLayout> lay(count);
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = parse(static_cast<const uint8_t*>(bufs[i]), (int64_t)lens[i], &P[i]);
+    if (rc != H2_OK) {
+      set_error("batch operator " + std::to_string(i) + ": " + h2_last_error());
+      return rc;
+    }
+    if ((rc = make_layout(P[i], &lay[i])) != H2_OK) return rc;
+  }
+  // arena offsets
+  auto up32 = [](int64_t x) { return (x + 31) / 32 * 32; };
+  std::vector<RowBases> base(count);
+  int64_t mat = 0, trans = 0, row = 0, pin = 0;
+  b->n.resize(count); b->pinv_off.resize(count); b->xt_row.resize(count); b->zn_row.resize(count);
+  for (int64_t i = 0; i < count; ++i) {
+    RowBases& B = base[i];
+    B.mat = mat;
+    B.trans = trans;
+    mat = up32(mat + lay[i].nmat);
+    trans = up32(trans + lay[i].ntrans);
+    B.xt = row; row += P[i].n;
+    B.xh = row; row += lay[i].H;
+    B.yh = row; row += lay[i].H;
+    B.zn = row; row += P[i].n;
+    b->n[i] = P[i].n;
+    b->pinv_off[i] = pin;
+    pin += P[i].n;
+    b->xt_row[i] = B.xt;
+    b->zn_row[i] = B.zn;
+    b->nmax = std::max(b->nmax, P[i].n);
+    b->total_n += P[i].n;
+    const int64_t q = P[i].q;
+    b->flops_per_vector += 2.0 * (double)(P[i].n * P[i].krow[q] + P[i].n * P[i].kcol[q] + P[i].ebase[q + 1] +
+                                          P[i].fbase[q + 1] + P[i].sdat[q + 1] + P[i].ddat[P[i].ndense]);
+  }
+  // rows of every operator, merged level by level
+  int64_t maxq = 0;
+  for (int64_t i = 0; i < count; ++i) maxq = std::max(maxq, P[i].q);
+  std::vector<std::vector<RowSpec>> up(maxq + 1), down(maxq);
+  std::vector<RowSpec> couple, dense, outr;
+  for (int64_t i = 0; i < count; ++i) {
+    RowsN R;
+    emit_rows_N(lay[i], base[i], &R);
+    for (size_t h = 0; h < R.up.size(); ++h) up[h].insert(up[h].end(), R.up[h].begin(), R.up[h].end());
+    for (size_t d = 0; d < R.down.size(); ++d) down[d].insert(down[d].end(), R.down[d].begin(), R.down[d].end());
+    couple.insert(couple.end(), R.couple.begin(), R.couple.end());
+    dense.insert(dense.end(), R.dense.begin(), R.dense.end());
+    outr.insert(outr.end(), R.out.begin(), R.out.end());
+  }
+  for (const auto* v : {&couple, &dense})
+    for (const RowSpec& r : *v)
+      if ((int64_t)r.blks.size() > kNbMax) {
+        set_error("batch: a row with more than 512 blocks");
+        return H2_EUNSUPPORTED;
+      }
+  for (int64_t h = 0; h <= maxq; ++h) add_phase(b, up[h], ARR_TRANS, MODE_STORE, false, true, b->up);
+  add_phase(b, couple, ARR_MAT, MODE_STORE, true, true, b->couple);
+  for (int64_t d = 0; d < maxq; ++d) add_phase(b, down[d], ARR_MAT, MODE_ACCUM, false, true, b->down);
+  add_phase(b, dense, ARR_MAT, MODE_STORE, true, false, b->dense);
+  add_phase(b, outr, ARR_MAT, MODE_ACCUM, false, true, b->out);
+
+  // device arena: matrix data, transposed bases, inverse permutations
+  HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_mat), sizeof(double) * std::max<int64_t>(mat, 1)), "hipMalloc(arena)");
+  HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_trans), sizeof(double) * std::max<int64_t>(trans, 1)), "hipMalloc(arena)");
+  std::vector<int32_t> pinv(std::max<int64_t>(pin, 1));
+  std::vector<double> tr;
+  for (int64_t i = 0; i < count; ++i) {
+    const uint8_t* bi = static_cast<const uint8_t*>(bufs[i]);
+    if (lay[i].nmat)
+      HIP_TRYB(hipMemcpy(b->d_mat + base[i].mat, bi + P[i].off_U, sizeof(double) * lay[i].nmat,
+                         hipMemcpyHostToDevice), "hipMemcpy(arena)");
+    if (lay[i].ntrans) {
+      tr.assign(lay[i].ntrans, 0.0);
+      build_transposed(bi, lay[i], tr.data());
+      HIP_TRYB(hipMemcpy(b->d_trans + base[i].trans, tr.data(), sizeof(double) * lay[i].ntrans,
+                         hipMemcpyHostToDevice), "hipMemcpy(arena)");
+    }
+    for (int64_t j = 0; j < P[i].n; ++j) pinv[b->pinv_off[i] + P[i].perm[j]] = (int32_t)j;
+  }
+  HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_pinv), sizeof(int32_t) * pinv.size()), "hipMalloc(pinv)");
+  HIP_TRYB(hipMemcpy(b->d_pinv, pinv.data(), sizeof(int32_t) * pinv.size(), hipMemcpyHostToDevice), "hipMemcpy");
+  // schedules
+  auto up_tab = [&](auto& v, auto** d) -> int {
+    if (v.empty()) return H2_OK;
+    HIP_TRYB(hipMalloc(reinterpret_cast<void**>(d), sizeof(v[0]) * v.size()), "hipMalloc(schedule)");
+    HIP_TRYB(hipMemcpy(*d, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice), "hipMemcpy(schedule)");
+    return H2_OK;
+  };
+  int rc;
+  if ((rc = up_tab(b->rt.rows, &b->rt.d_rows)) || (rc = up_tab(b->rt.colend, &b->rt.d_colend)) ||
+      (rc = up_tab(b->rt.in_off, &b->rt.d_in_off)))
+    return rc;
+  // workspace (row-major, nvp per row), zeroed once
+  HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_ws), sizeof(double) * std::max<int64_t>(row, 1) * b->nvp),
+           "hipMalloc(workspace)");
+  HIP_TRYB(hipMemset(b->d_ws, 0, sizeof(double) * std::max<int64_t>(row, 1) * b->nvp), "hipMemset(workspace)");
+  HIP_TRYB(hipHostMalloc(reinterpret_cast<void**>(&b->h_items), sizeof(BatchItem) * count, hipHostMallocDefault),
+           "hipHostMalloc(items)");
+  HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_items), sizeof(BatchItem) * count), "hipMalloc(items)");
+  HIP_TRYB(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "hipStreamCreate");
+  HIP_TRYB(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "hipEventCreate");
+  HIP_TRYB(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "hipEventCreate");
+  HIP_TRYB(hipEventCreateWithFlags(&b->ev_items, hipEventDisableTiming), "hipEventCreate");
+  HIP_TRYB(hipDeviceSynchronize(), "hipDeviceSynchronize(batch load)");
+  return H2_OK;
+}
+
+int run_blaunch(h2_batch_s* b, const Launch& L, hipStream_t s) {
+  const double* data = L.arr == ARR_TRANS ? b->d_trans : b->d_mat;
+  hipError_t e = launch_rows_mfma<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend, b->rt.d_in_off,
+                                          data, b->d_ws, b->d_ws, (int)b->nvp, L.mode, L.max_rows, s, L.kc, L.grid);
+  if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
+  return H2_OK;
+}
+
+// The launch sequence after the items are on the device.
+int batch_sequence(h2_batch_s* b, hipStream_t s) {
+  int rc;
+  HIP_TRYB(launch_batch_permute(b->d_items, b->count, b->nmax, b->d_pinv, b->d_ws, (int)b->nvp, false, s),
+           "batch permute");
+  HIP_TRYB(hipEventRecord(b->ev_fork, s), "hipEventRecord");
+  HIP_TRYB(hipStreamWaitEvent(b->side, b->ev_fork, 0), "hipStreamWaitEvent");
+  for (const Launch& L : b->dense)
+    if ((rc = run_blaunch(b, L, b->side))) return rc;
+  HIP_TRYB(hipEventRecord(b->ev_join, b->side), "hipEventRecord");
+  for (const auto* v : {&b->up, &b->couple, &b->down})
+    for (const Launch& L : *v)
+      if ((rc = run_blaunch(b, L, s))) return rc;
+  HIP_TRYB(hipStreamWaitEvent(s, b->ev_join, 0), "hipStreamWaitEvent");
+  for (const Launch& L : b->out)
+    if ((rc = run_blaunch(b, L, s))) return rc;
+  HIP_TRYB(launch_batch_permute(b->d_items, b->count, b->nmax, b->d_pinv, b->d_ws, (int)b->nvp, true, s),
+           "batch permute out");
+  return H2_OK;
+}
+
+int fill_items(h2_batch_s* b, const h2_batch_item* items) {
+  // the previous call's copy of the items must have left the pinned buffer
+  if (b->items_pending) HIP_TRYB(hipEventSynchronize(b->ev_items), "hipEventSynchronize(items)");
+  for (int64_t i = 0; i < b->count; ++i) {
+    const h2_batch_item& it = items[i];
+    if (it.nv < 0 || it.nv > b->nv_max) {
+      set_error("batch item " + std::to_string(i) + ": nv outside [0, nv_max]");
+      return H2_EINVAL;
+    }
+    if (it.nv > 0) {
+      if (!it.Y || it.ldy < b->n[i] || (it.alpha != 0.0 && (!it.X || it.ldx < b->n[i]))) {
+        set_error("batch item " + std::to_string(i) + ": bad pointer or leading dimension");
+        return H2_EINVAL;
+      }
+    }
+    BatchItem& d = b->h_items[i];
+    d.X = it.X; d.Y = it.Y; d.ldx = it.ldx; d.ldy = it.ldy; d.nv = it.nv;
+    d.alpha = it.alpha; d.beta = it.beta; d.n = b->n[i];
+    d.pinv_off = b->pinv_off[i]; d.xt_row = b->xt_row[i]; d.zn_row = b->zn_row[i];
+  }
+  return H2_OK;
+}
+
+}  // namespace
+}  // namespace h2
+
+using namespace h2;
+
+extern "C" {
+
+int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, int64_t nv_max, int device,
+                  h2_batch* out) {
+  if (!out || !bufs || !lens || count < 1 || nv_max < 1 || nv_max > kPassVectorsMfma) {
+    set_error("h2_batch_load: bad arguments");
+    return H2_EINVAL;
+  }
+  *out = nullptr;
+  for (int64_t i = 0; i < count; ++i)
+    if (!bufs[i]) { set_error("h2_batch_load: null buffer"); return H2_EINVAL; }
+  int ndev = 0;
+  HIP_TRYB(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) { set_error("device ordinal out of range"); return H2_EINVAL; }
+  DevGuard guard(device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  h2_batch_s* b = new (std::nothrow) h2_batch_s();
+  if (!b) { set_error("out of host memory"); return H2_ENOMEM; }
+  b->device = device;
+  b->count = count;
+  b->nv_max = nv_max;
+  b->nvp = (nv_max + 15) / 16 * 16;
+  int rc;
+  try {
+    rc = batch_build(bufs, lens, count, b);
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory while building the batch");
+    rc = H2_ENOMEM;
+  }
+  if (rc != H2_OK) {
+    (void)hipDeviceSynchronize();
+    free_batch(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return H2_OK;
+}
+
+int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream) {
+  if (!b || !items) { set_error("null batch or items"); return H2_EINVAL; }
+  DevGuard guard(b->device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = fill_items(b, items);
+  if (rc != H2_OK) return rc;
+  if (b->use_graph && b->graph && b->graph_stream == s) {
+    HIP_TRYB(hipGraphLaunch(b->graph, s), "hipGraphLaunch");
+    // the next call may refill the pinned items once this replay has run
+    HIP_TRYB(hipEventRecord(b->ev_items, s), "hipEventRecord(items)");
+    b->items_pending = true;
+    return H2_OK;
+  }
+  const bool capture = b->use_graph && s != nullptr;
+  if (capture) HIP_TRYB(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  auto body = [&]() -> int {
+    HIP_TRYB(hipMemcpyAsync(b->d_items, b->h_items, sizeof(BatchItem) * b->count, hipMemcpyHostToDevice, s),
+             "hipMemcpyAsync(items)");
+    HIP_TRYB(hipEventRecord(b->ev_items, s), "hipEventRecord(items)");
+    return batch_sequence(b, s);
+  };
+  rc = body();
+  if (capture) {
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != H2_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail_b(e, "hipStreamEndCapture");
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return hip_fail_b(ei, "hipGraphInstantiate");
+    b->graph_stream = s;
+    HIP_TRYB(hipGraphLaunch(b->graph, s), "hipGraphLaunch");
+    HIP_TRYB(hipEventRecord(b->ev_items, s), "hipEventRecord(items)");
+  } else if (rc != H2_OK) {
+    return rc;
+  }
+  b->items_pending = true;
+  return H2_OK;
+}
+
+int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
+  if (!b || !items) { set_error("null batch or items"); return H2_EINVAL; }
+  DevGuard guard(b->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool graph_was = b->use_graph;
+  b->use_graph = false;
+  if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+  int rc = h2_batch_gemv(b, items, stream);  // fills the workspace with this call's data
+  if (rc != H2_OK) { b->use_graph = graph_was; return rc; }
+  HIP_TRYB(hipStreamSynchronize(s), "hipStreamSynchronize");
+  hipEvent_t e0, e1;
+  HIP_TRYB(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRYB(hipEventCreate(&e1), "hipEventCreate");
+  const int kcs[2] = {32, 64};
+  const int64_t grids[4] = {0, 1024, 2048, 4096};
+  for (auto* v : {&b->up, &b->couple, &b->down, &b->dense, &b->out})
+    for (Launch& L : *v) {
+      float best = 1e30f;
+      int best_kc = L.kc;
+      int64_t best_grid = L.grid;
+      for (int kc : kcs)
+        for (int64_t gsz : grids) {
+          if (gsz != 0 && gsz >= L.row_count) continue;
+          Launch T = L;
+          T.kc = kc;
+          T.grid = gsz;
+          float tsum = 0.0f;
+          for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
+            if ((rc = run_blaunch(b, T, s))) return rc;
+            HIP_TRYB(hipEventRecord(e1, s), "hipEventRecord");
+            HIP_TRYB(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            HIP_TRYB(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (rep > 0) tsum += ms;  // first repetition warms up
+          }
+          if (tsum < best) {
+            best = tsum;
+            best_kc = kc;
+            best_grid = gsz;
+          }
+        }
+      L.kc = best_kc;
+      L.grid = best_grid;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->use_graph = graph_was;
+  return H2_OK;
+}
+
+int h2_batch_graph(h2_batch b, int enable) {
+  if (!b) { set_error("null batch"); return H2_EINVAL; }
+  DevGuard guard(b->device);
+  HIP_TRYB(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  b->use_graph = enable != 0;
+  if (b->graph) { (void)hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+  return H2_OK;
+}
+
+int h2_batch_info(h2_batch b, int64_t* count, int64_t* total_n, double* flops_per_vector, int64_t* launches) {
+  if (!b) { set_error("null batch"); return H2_EINVAL; }
+  if (count) *count = b->count;
+  if (total_n) *total_n = b->total_n;
+  if (flops_per_vector) *flops_per_vector = b->flops_per_vector;
+  if (launches)
+    *launches = 2 + (int64_t)(b->up.size() + b->couple.size() + b->down.size() + b->dense.size() + b->out.size());
+  return H2_OK;
+}
+
+int h2_batch_free(h2_batch b) {
+  if (!b) return H2_OK;
+  {
+    DevGuard guard(b->device);
+    (void)hipDeviceSynchronize();
+    free_batch(b);
+  }
+  delete b;
+  return H2_OK;
+}
+
+}  // extern "C"

@@ -1,6 +1,6 @@
 // Library-private declarations of libh2gemv: the host view of a serialized
-// representation, the launch schedules built at load time, the handle, and
-// the kernel launchers.
+// representation, the launch plans built at load time, the handle, and the
+// kernel launchers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,8 +17,15 @@ namespace h2 {
 // Largest rank and leaf size the kernels accept (one output entry per
 // thread of a 256-thread workgroup along the row dimension).
 constexpr int kMaxDim = 256;
-// Vectors per pass of the workspace; larger nv is processed in chunks.
-constexpr int kNvChunk = 64;
+// Largest number of blocks in one row handled by the LDS-tabled streaming
+// kernel; wider rows (never produced by the builder) take a simpler kernel.
+constexpr int kNbMax = 512;
+// Largest number of children of one node.
+constexpr int kMaxChildren = kNbMax;
+// Vectors per pass of the streaming path (one thread keeps them in registers).
+constexpr int kPassVectors = 4;
+// Vectors per pass of the MFMA path (four 16-wide tiles).
+constexpr int kPassVectorsMfma = 64;
 
 void set_error(const std::string& msg);
 
@@ -41,32 +48,34 @@ struct Parsed {
 // Parse and validate; returns H2_OK, H2_EFORMAT, H2_EUNSUPPORTED, H2_ENOMEM.
 int parse(const uint8_t* buf, int64_t len, Parsed* p);
 
-// A block row (or, transposed, a block column) processed by one workgroup.
+// One output row-block processed by one workgroup: out[out_off + a + out_ld*v]
+// (a < nrows) from the column-major nrows x ncols matrix at data + data_off
+// (its blocks are contiguous) times the input gathered block by block.
 struct RowDesc {
-  int64_t data_off;  // streaming kernel: element offset of the row's first block
-  int64_t out_off;   // row offset of the output (element (a, v) at out_off + a + out_ld*v)
-  int32_t nrows;     // output length (rows of the stored blocks, or columns when transposed)
-  int32_t blk_begin; // blocks [blk_begin, blk_end) in the per-block arrays
+  int64_t data_off;  // element offset of the row's first stored block (streaming)
+  int64_t out_off;   // output row offset
+  int32_t nrows;     // output length
+  int32_t blk_begin; // blocks [blk_begin, blk_end) in the per-block tables
   int32_t blk_end;
   int32_t pad;
   int64_t out_ld;    // output stride between vectors
   int64_t in_ld;     // input stride between vectors
 };
 
-// Schedule for the streaming kernel (op 'N'): the blocks of a row are
-// contiguous in memory and form one column-major nrows x ncols matrix.
-struct StreamSched {
+// Row schedules of the streaming kernel: per block, the cumulative end
+// column within its row and the input row offset of its first column.
+struct RowTables {
   std::vector<RowDesc> rows;
-  std::vector<int32_t> colend;   // per block: cumulative end column within its row
-  std::vector<int64_t> in_off;   // per block: input row offset of its first column
+  std::vector<int32_t> colend;
+  std::vector<int64_t> in_off;
   RowDesc* d_rows = nullptr;
   int32_t* d_colend = nullptr;
   int64_t* d_in_off = nullptr;
 };
 
-// Schedule for the transposed product (op 'T'): the blocks of a block
+// Row schedules of the transposed (gather) kernel: the blocks of a block
 // column, each read transposed.
-struct GatherSched {
+struct GatherTables {
   std::vector<RowDesc> rows;
   std::vector<int64_t> data;     // per block: element offset of the stored block
   std::vector<int32_t> mr;       // per block: rows of the stored block
@@ -77,11 +86,99 @@ struct GatherSched {
   int64_t* d_in_off = nullptr;
 };
 
+// Where a launch reads and writes.
+enum Buf { BUF_XT = 0, BUF_XH = 1, BUF_YH = 2, BUF_ZN = 3 };
+enum Arr { ARR_MAT = 0, ARR_TRANS = 1 };
+enum Mode { MODE_STORE = 0, MODE_ACCUM = 1, MODE_FINAL = 2 };
+enum Kind { KIND_STREAM = 0, KIND_GATHER = 1, KIND_WIDE = 2 };
+
+struct Launch {
+  int kind = KIND_STREAM;
+  int arr = ARR_MAT;
+  int in = BUF_XT, out = BUF_XH;
+  int mode = MODE_STORE;
+  int64_t row_begin = 0, row_count = 0;  // slice of the kind's row table
+  int32_t max_rows = 0;                   // largest output length of its rows
+  bool lowrank = true;                    // false for the dense near-field phase (always FP64)
+  int kc = 64;                            // MFMA path: columns per LDS chunk (tuned in batches)
+  int64_t grid = 0;                       // MFMA path: workgroups (0 = one per row; fewer = persistent)
+};
+
+// The launch sequence of one operation (op 'N' or 'T').
+struct Plan {
+  std::vector<Launch> up;      // leaf products, then transfer levels q..1
+  std::vector<Launch> couple;  // all levels at once (plus wide rows, if any)
+  std::vector<Launch> down;    // transfer levels 1..q
+  std::vector<Launch> dense;   // dense leaf blocks (side stream)
+  Launch out;                  // leaf expansion + dense partial + alpha/beta update
+};
+
+struct Epilogue {
+  const double* zn;     // dense partial, n x nv (ld n)
+  const int32_t* perm;  // tree position -> original index
+  double alpha, beta;
+  double* Y;
+  int64_t ldy;
+  int64_t n;
+};
+
 struct LevelInfo {
   int64_t begin, count;  // nodes [begin, begin+count)
   int64_t krow, kcol, kmax;
-  int64_t e_off, f_off;  // element offsets (in the device matrix array) of the level's transfers
 };
+
+// ---- plan construction (h2_plan.cpp)
+
+struct BlockRef {
+  int64_t data;    // element offset of the stored block (gather rows)
+  int64_t in_off;  // input row offset
+  int32_t width;   // columns of the stored block
+  int32_t mr;      // rows of the stored block (gather rows)
+};
+
+struct RowSpec {
+  int64_t data_off, out_off, out_ld, in_ld;
+  int32_t nrows;
+  std::vector<BlockRef> blks;
+};
+
+// Per-operator offsets used to emit rows.
+struct OpLayout {
+  const Parsed* P = nullptr;
+  bool shared = true;
+  std::vector<int64_t> kmax;   // per level
+  std::vector<int64_t> hoff;   // per node: first row in the vector trees
+  std::vector<int64_t> cbeg;   // per node: first child (children contiguous); nnodes+1 entries
+  int64_t H = 0;               // rows of the vector trees
+  int64_t oU = 0, oE = 0, oV = 0, oF = 0, oS = 0, oD = 0, nmat = 0;  // matrix array (elements)
+  int64_t tUT = 0, tET = 0, tVT = 0, tFT = 0, ntrans = 0;            // transposed array (elements)
+  int64_t eoff(int64_t c, int64_t l) const;  // offset of E_c within the E section
+  int64_t foff(int64_t c, int64_t l) const;  // offset of F_c within the F section
+};
+
+// Where an operator's data and workspace sit: element offsets of its matrix
+// and transposed arrays, row offsets of its X~, x^, y^ and dense-partial
+// regions, and the vector strides of the column-major streaming layout.
+struct RowBases {
+  int64_t mat = 0, trans = 0;
+  int64_t xt = 0, xh = 0, yh = 0, zn = 0;
+  int64_t ld_x = 0, ld_h = 0;
+};
+
+// Rows of every op-'N' phase of one operator.
+struct RowsN {
+  std::vector<std::vector<RowSpec>> up;    // up[0]: leaf products; up[h]: transfer level q-h+1 -> q-h
+  std::vector<RowSpec> couple;             // all levels
+  std::vector<std::vector<RowSpec>> down;  // down[l-1]: transfer level l
+  std::vector<RowSpec> dense;
+  std::vector<RowSpec> out;                // leaf expansion
+};
+
+int make_layout(const Parsed& P, OpLayout* L);
+void build_transposed(const uint8_t* buf, const OpLayout& L, double* tr);
+void emit_rows_N(const OpLayout& L, const RowBases& B, RowsN* R);
+void append_row(RowTables& t, const RowSpec& r);
+int64_t row_work(const RowSpec& r);
 
 }  // namespace h2
 
@@ -93,23 +190,30 @@ struct h2_op_s {
   std::vector<h2::LevelInfo> lv;
   h2_stats_t stats{};
   // device data
-  double* d_mat = nullptr;   // U, E, V, F, S, D (one allocation, section layout kept)
-  int64_t u_off = 0, v_off = 0, s_off = 0, d_off = 0;  // element offsets into d_mat
+  double* d_mat = nullptr;    // U, E, V, F, S, D (section layout of the buffer kept)
+  double* d_trans = nullptr;  // transposed copies: U^T, E^T (and V^T, F^T)
+  int64_t n_lowrank = 0;      // elements of d_mat before the dense section (U, E, V, F, S)
+  int64_t n_trans = 0;        // elements of d_trans
+  float* d_mat32 = nullptr;   // FP32 copies of d_mat[0, n_lowrank) and of d_trans
+  float* d_trans32 = nullptr;
   int32_t* d_perm = nullptr;
-  int32_t* d_lo = nullptr;
-  int32_t* d_m = nullptr;
-  int32_t* d_parent = nullptr;
-  int32_t* d_cptr = nullptr;   // children of p: [cptr[p], cptr[p+1])
-  int64_t* d_hoff = nullptr;   // per node: first row in the vector trees
-  h2::StreamSched coupleN, denseN;
-  h2::GatherSched coupleT, denseT;
+  int32_t* d_pinv = nullptr;  // original index -> tree position
+  bool mfma_ok = true;        // every op-'N' launch fits the MFMA row kernel
+  h2::RowTables rt;           // streaming rows of both plans
+  h2::RowTables wide;         // rows too wide for the tabled kernel
+  h2::GatherTables gt;        // transposed rows of the 'T' plan
+  h2::Plan planN, planT;
   int64_t index_bytes = 0;
-  // workspace (n x cap, H x cap, H x cap, n x cap)
+  hipStream_t side = nullptr;              // dense phase runs here, concurrently
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // workspace: X~ and the dense partial (n x cap), x^ and y^ (H x cap), in
+  // doubles per row; the streaming path uses them column-major with 4
+  // columns, the MFMA path row-major with up to 64
   int64_t cap = 0;
   double *d_xt = nullptr, *d_xh = nullptr, *d_yh = nullptr, *d_zn = nullptr;
   // profiling
   bool profiling = false;
-  std::vector<std::array<hipEvent_t, 7>> ev_pool;
+  std::vector<std::array<hipEvent_t, 9>> ev_pool;
   size_t ev_used = 0;
   h2_profile_t prof{};
 };
@@ -117,25 +221,41 @@ struct h2_op_s {
 namespace h2 {
 
 // kernel launchers (h2_kernels.hip); all asynchronous on `s`
-hipError_t launch_permute_in(const double* X, int64_t ldx, const int32_t* perm, double* xt, int64_t n,
-                             int nv, hipStream_t s);
+hipError_t launch_permute_in(const double* X, int64_t ldx, const int32_t* perm, double* xt, int64_t n, int nv,
+                             hipStream_t s);
 hipError_t launch_scale(double* Y, int64_t ldy, int64_t n, int64_t nv, double beta, hipStream_t s);
-hipError_t launch_leaf_up(const double* B, int k, int64_t leaf0, int64_t nleaves, const int32_t* lo,
-                          const int32_t* m, const int64_t* hoff, const double* xt, int64_t n, double* xh,
-                          int64_t H, int nv, hipStream_t s);
-hipError_t launch_transfer_up(const double* T, int kc, int kp, int64_t pbegin, int64_t pcount,
-                              int64_t cbegin, const int32_t* cptr, const int64_t* hoff, double* xh,
-                              int64_t H, int nv, hipStream_t s);
-hipError_t launch_transfer_down(const double* T, int kc, int kp, int64_t cbegin, int64_t ccount,
-                                const int32_t* parent, const int64_t* hoff, double* yh, int64_t H, int nv,
-                                hipStream_t s);
-hipError_t launch_leaf_down(const double* B, int k, int64_t leaf0, int64_t nleaves, const int32_t* lo,
-                            const int32_t* m, const int64_t* hoff, const double* yh, int64_t H,
-                            const double* zn, int64_t n, const int32_t* perm, double alpha, double beta,
-                            double* Y, int64_t ldy, int nv, hipStream_t s);
-hipError_t launch_stream_rows(const StreamSched& sc, const double* data, const double* in, double* out,
-                              int nv, hipStream_t s);
-hipError_t launch_gather_rows(const GatherSched& sc, const double* data, const double* in, double* out,
-                              int nv, hipStream_t s);
+template <typename T>
+hipError_t launch_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                       const T* data, const double* in, double* out, int nv, int mode, const Epilogue& ep,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                            const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
+                            hipStream_t s, int kc = 64, int64_t grid = 0);
+
+// One operator's part of a batched call, as the batched permutation kernels see it.
+struct BatchItem {
+  const double* X;
+  double* Y;
+  int64_t ldx, ldy, nv;
+  double alpha, beta;
+  int64_t n;         // operator order
+  int64_t pinv_off;  // its inverse permutation in the concatenated array
+  int64_t xt_row;    // its X~ rows in the workspace arena
+  int64_t zn_row;    // its dense-partial rows in the workspace arena
+};
+hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t nmax, const int32_t* pinv,
+                                double* ws, int nvp, bool out, hipStream_t s);
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pinv, double* xt, int64_t n, int nv,
+                                int nvp, hipStream_t s);
+hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double alpha, double beta, double* Y,
+                                 int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s);
+hipError_t launch_rows_wide(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                            const double* data, const double* in, double* out, int nv, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const RowDesc* rows, int64_t nrows, const int64_t* bdata, const int32_t* bmr,
+                         const int64_t* bin, const T* data, const double* in, double* out, int nv,
+                         hipStream_t s);
 
 }  // namespace h2

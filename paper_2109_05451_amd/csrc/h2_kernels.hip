@@ -6,13 +6,21 @@
 // output are n x nv column-major.  Every output entry is produced by exactly
 // one thread with a fixed summation order: no atomics, bitwise-reproducible
 // results.
+//
+// Every phase of the product with op 'N' is one shape of work: a block row
+// whose stored blocks are contiguous in HBM, i.e. one column-major
+// nrows x ncols matrix M, times an input gathered block by block.  Leaf
+// products (with the transposed leaf bases), the transfer up- and downsweep
+// levels, the coupling products of all levels (Algorithm 4: levels are
+// independent) and the dense leaf rows are all row lists of one streaming
+// kernel; only the epilogue differs (store, accumulate, or the final
+// permuted alpha/beta update).
 #include "h2_internal.h"
 
 namespace h2 {
 namespace {
 
-constexpr int kRowThreads = 256;
-constexpr int kSmallThreads = 64;
+constexpr int kT = 256;  // threads per workgroup (4 wave64)
 
 // X~[i, v] = X[perm[i], v]: the input in tree order (sub-vectors are taken
 // from the node index sets, Section 3).
@@ -32,156 +40,394 @@ __global__ void k_scale(double* __restrict__ Y, int64_t ldy, int64_t n, int64_t 
   *y = beta == 0.0 ? 0.0 : beta * *y;
 }
 
-// Leaf products x^_t = B_t^T x~_t (Algorithm 1, first batched product).
-// One workgroup per leaf; B_t is m x k column-major at B + lo*k.
-__global__ void k_leaf_up(const double* __restrict__ B, int k, int64_t leaf0, const int32_t* __restrict__ lo,
-                          const int32_t* __restrict__ msz, const int64_t* __restrict__ hoff,
-                          const double* __restrict__ xt, int64_t n, double* __restrict__ xh, int64_t H, int nv) {
-  const int64_t t = leaf0 + blockIdx.x;
-  const int l0 = lo[t], m = msz[t];
-  const double* Bt = B + (int64_t)l0 * k;
-  for (int o = threadIdx.x; o < k * nv; o += blockDim.x) {
-    const int a = o % k, v = o / k;
-    const double* x = xt + l0 + n * v;
-    const double* col = Bt + (int64_t)m * a;
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) s += col[i] * x[i];
-    xh[hoff[t] + a + H * v] = s;
-  }
+// Vector loads of W consecutive elements (16 bytes for W = 16/sizeof(T)),
+// nontemporal: the matrix data is streamed once per product.
+template <typename T, int W> struct Vec { typedef T v __attribute__((ext_vector_type(W))); };
+template <typename T> struct Vec<T, 1> { typedef T v; };
+template <typename T, int W>
+__device__ __forceinline__ typename Vec<T, W>::v ld_stream(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const typename Vec<T, W>::v*>(p));
 }
+template <typename V>
+__device__ __forceinline__ auto lane_elem(const V& v, int i) { return v[i]; }
+__device__ __forceinline__ double lane_elem(const double& v, int) { return v; }
+__device__ __forceinline__ float lane_elem(const float& v, int) { return v; }
 
-// Transfer upsweep of one level (Algorithm 1, the loop over levels):
-// x^_p = sum over children c of T_c^T x^_c, T_c is kc x kp column-major.
-// One workgroup per parent; the parent owns its sum, so no atomics.
-__global__ void k_transfer_up(const double* __restrict__ T, int kc, int kp, int64_t pbegin, int64_t cbegin,
-                              const int32_t* __restrict__ cptr, const int64_t* __restrict__ hoff,
-                              double* __restrict__ xh, int64_t H, int nv) {
-  const int64_t p = pbegin + blockIdx.x;
-  const int c0 = cptr[p], c1 = cptr[p + 1];
-  for (int o = threadIdx.x; o < kp * nv; o += blockDim.x) {
-    const int b = o % kp, v = o / kp;
-    double s = 0.0;
-    for (int c = c0; c < c1; ++c) {
-      const double* col = T + (int64_t)(c - cbegin) * kc * kp + (int64_t)kc * b;
-      const double* x = xh + hoff[c] + H * v;
-      for (int a = 0; a < kc; ++a) s += col[a] * x[a];
+// Accumulation type: FP64 data accumulates in FP64, FP32 data in FP32.
+template <typename T> struct Acc { typedef T t; };
+
+// Columns [0, cn) of M for one thread: rows W*p .. W*p+W-1 (one 16-byte
+// load per column when W*sizeof(T) = 16), columns g, g+G, g+2G, ...  Four
+// columns are loaded before any is used, so each thread keeps four loads in
+// flight.
+template <typename T, int NVB, int W, int XS>
+__device__ __forceinline__ void stream_cols(const T* __restrict__ Mrow, int64_t m, int cn, int g, int G,
+                                            const typename Acc<T>::t* xs, typename Acc<T>::t (&acc)[NVB][4]) {
+  typedef typename Acc<T>::t A;
+  typedef typename Vec<T, W>::v V;
+  constexpr int U = 4;
+  int j = g;
+  for (; j + (U - 1) * G < cn; j += U * G) {
+    V mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) mv[u] = ld_stream<T, W>(Mrow + m * (j + u * G));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < NVB; ++v) {
+        const A x = xs[v * XS + j + u * G];
+#pragma unroll
+        for (int r = 0; r < W; ++r) acc[v][r] = __builtin_fma((A)lane_elem(mv[u], r), x, acc[v][r]);
+      }
+  }
+  for (; j < cn; j += G) {
+    const V mv = ld_stream<T, W>(Mrow + m * j);
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const A x = xs[v * XS + j];
+#pragma unroll
+      for (int r = 0; r < W; ++r) acc[v][r] = __builtin_fma((A)lane_elem(mv, r), x, acc[v][r]);
     }
-    xh[hoff[p] + b + H * v] = s;
   }
 }
 
-// Transfer downsweep of one level (Algorithm 6): y^_c += T_c y^_parent.
-__global__ void k_transfer_down(const double* __restrict__ T, int kc, int kp, int64_t cbegin,
-                                const int32_t* __restrict__ parent, const int64_t* __restrict__ hoff,
-                                double* __restrict__ yh, int64_t H, int nv) {
-  const int64_t c = cbegin + blockIdx.x;
-  const int p = parent[c];
-  const double* Tc = T + (int64_t)blockIdx.x * kc * kp;
-  for (int o = threadIdx.x; o < kc * nv; o += blockDim.x) {
-    const int a = o % kc, v = o / kc;
-    const double* y = yh + hoff[p] + H * v;
-    double s = 0.0;
-    for (int b = 0; b < kp; ++b) s += Tc[a + (int64_t)kc * b] * y[b];
-    yh[hoff[c] + a + H * v] += s;
-  }
-}
-
-// Leaf expansion and output (Algorithm 6, last product), fused with the
-// dense-phase partial and the BLAS update, written in original order:
-// Y[perm[lo+i], v] = alpha * (zn[lo+i, v] + (B_t y^_t)[i, v]) + beta * Y[...].
-__global__ void k_leaf_down(const double* __restrict__ B, int k, int64_t leaf0, const int32_t* __restrict__ lo,
-                            const int32_t* __restrict__ msz, const int64_t* __restrict__ hoff,
-                            const double* __restrict__ yh, int64_t H, const double* __restrict__ zn, int64_t n,
-                            const int32_t* __restrict__ perm, double alpha, double beta, double* __restrict__ Y,
-                            int64_t ldy, int nv) {
-  const int64_t t = leaf0 + blockIdx.x;
-  const int l0 = lo[t], m = msz[t];
-  const double* Bt = B + (int64_t)l0 * k;
-  for (int o = threadIdx.x; o < m * nv; o += blockDim.x) {
-    const int i = o % m, v = o / m;
-    const double* y = yh + hoff[t] + H * v;
-    double s = zn[l0 + i + n * v];
-    for (int a = 0; a < k; ++a) s += Bt[i + (int64_t)m * a] * y[a];
-    double* yo = Y + perm[l0 + i] + ldy * v;
-    *yo = beta == 0.0 ? alpha * s : alpha * s + beta * *yo;
-  }
-}
-
-// Block-row streaming product, for the coupling blocks of all levels at once
-// (Algorithm 4: the levels are independent) and for the dense leaf blocks.
-// The blocks of a row are contiguous and together form a column-major
-// nrows x ncols matrix M; out[:, v] = M * in_gathered[:, v].  Thread
-// (a, g) owns row a and columns g, g+G, g+2G, ...: consecutive threads read
-// consecutive addresses, so the workgroup streams M with coalesced loads.
-// Partial sums over g are combined in LDS in a fixed order.
-template <int NVB>
-__global__ __launch_bounds__(kRowThreads) void k_stream_rows(
-    const RowDesc* __restrict__ rows, const int32_t* __restrict__ colend, const int64_t* __restrict__ in_off,
-    const double* __restrict__ data, const double* __restrict__ in, double* __restrict__ out, int nv) {
-  __shared__ double red[kRowThreads * NVB];
+// The streaming kernel.  Workgroup = one row; thread (p, g) owns rows
+// W*p .. W*p+W-1 of M and every G-th column.  The row's input is gathered
+// into LDS chunk by chunk (block lookup by binary search over the row's
+// block table, also in LDS); M is read once, with coalesced nontemporal
+// 16-byte loads when the row's size and offset allow it.  Partial sums over
+// g are combined in LDS in a fixed order, then the epilogue stores,
+// accumulates, or applies the final permuted update
+// Y[perm[i]] = alpha*(s + zn[i]) + beta*Y[perm[i]] (in FP64).
+// T = double: the FP64 path; T = float: the low-rank phases of the FP32
+// path (vector trees stay FP64 in memory; products accumulate in FP32).
+template <typename T, int NVB>
+__global__ __launch_bounds__(kT) void k_rows(const RowDesc* __restrict__ rows, const int32_t* __restrict__ colend,
+                                             const int64_t* __restrict__ in_off, const T* __restrict__ data,
+                                             const double* in, double* out, int nv, int mode, Epilogue ep) {
+  typedef typename Acc<T>::t A;
+  constexpr int VW = 16 / sizeof(T);                // elements per 16-byte load
+  constexpr int XS = 2048 * 8 / sizeof(A) / NVB;    // LDS columns per chunk (16 KB)
+  __shared__ A xs[XS * NVB];
+  __shared__ int32_t s_end[kNbMax];
+  __shared__ int64_t s_in[kNbMax];
   const RowDesc R = rows[blockIdx.x];
   const int m = R.nrows;
   if (m <= 0) return;
   const int tid = threadIdx.x;
-  const int G = kRowThreads / m;
-  const int a = tid % m, g = tid / m;
-  const int nb = R.blk_end - R.blk_begin;
-  const int ncols = nb > 0 ? colend[R.blk_end - 1] : 0;
-  const double* M = data + R.data_off;
-  for (int v0 = 0; v0 < nv; v0 += NVB) {
-    const int nvb = min(NVB, nv - v0);
-    double acc[NVB];
+  const int nb = R.blk_end - R.blk_begin;  // <= kNbMax, checked when the schedule is built
+  for (int i = tid; i < nb; i += kT) {
+    s_end[i] = colend[R.blk_begin + i];
+    s_in[i] = in_off[R.blk_begin + i];
+  }
+  __syncthreads();
+  const int ncols = nb > 0 ? s_end[nb - 1] : 0;
+  // widest row group that divides m and keeps the loads aligned
+  int W = VW;
+  while (W > 1 && ((m % W) != 0 || (R.data_off % W) != 0)) W >>= 1;
+  const int P = m / W;
+  const int G = kT / P;
+  const int p = tid % P, g = tid / P;
+  const T* Mrow = data + R.data_off + W * p;
+  A acc[NVB][4];
 #pragma unroll
-    for (int v = 0; v < NVB; ++v) acc[v] = 0.0;
-    if (g < G && nb > 0) {
-      int b = R.blk_begin, bstart = 0, bend = colend[b];
-      for (int j = g; j < ncols; j += G) {
-        while (j >= bend) {
-          bstart = bend;
-          ++b;
-          bend = colend[b];
-        }
-        const double mv = M[(int64_t)a + (int64_t)m * j];
-        const double* x = in + in_off[b] + (j - bstart) + R.in_ld * v0;
+  for (int v = 0; v < NVB; ++v)
 #pragma unroll
-        for (int v = 0; v < NVB; ++v)
-          if (v < nvb) acc[v] += mv * x[R.in_ld * v];
+    for (int r = 0; r < 4; ++r) acc[v][r] = 0;
+
+  for (int c0 = 0; c0 < ncols; c0 += XS) {
+    const int cn = min(XS, ncols - c0);
+    if (c0 > 0) __syncthreads();  // previous chunk fully consumed
+    for (int j = tid; j < cn; j += kT) {
+      const int col = c0 + j;
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[mid] > col) hi = mid; else lo = mid + 1;
       }
+      const int bstart = lo > 0 ? s_end[lo - 1] : 0;
+      const double* src = in + s_in[lo] + (col - bstart);
+#pragma unroll
+      for (int v = 0; v < NVB; ++v) xs[v * XS + j] = v < nv ? (A)src[R.in_ld * v] : (A)0;
     }
     __syncthreads();
     if (g < G) {
-#pragma unroll
-      for (int v = 0; v < NVB; ++v) red[(g * NVB + v) * m + a] = acc[v];
+      const T* Mc = Mrow + (int64_t)m * c0;
+      if (W == VW) stream_cols<T, NVB, VW, XS>(Mc, m, cn, g, G, xs, acc);
+      else if (VW >= 4 && W == 2) stream_cols<T, NVB, (VW >= 4 ? 2 : 1), XS>(Mc, m, cn, g, G, xs, acc);
+      else stream_cols<T, NVB, 1, XS>(Mc, m, cn, g, G, xs, acc);
     }
-    __syncthreads();
-    for (int o = tid; o < m * nvb; o += kRowThreads) {
-      const int aa = o % m, v = o / m;
-      double s = 0.0;
-      for (int gg = 0; gg < G; ++gg) s += red[(gg * NVB + v) * m + aa];
-      out[R.out_off + aa + R.out_ld * (v0 + v)] = s;
+  }
+  __syncthreads();
+  A* red = xs;  // G*m <= W*kT, so NVB*G*m <= XS*NVB
+  if (g < G) {
+#pragma unroll
+    for (int v = 0; v < NVB; ++v)
+      for (int r = 0; r < W; ++r) red[(v * G + g) * m + W * p + r] = acc[v][r];
+  }
+  __syncthreads();
+  for (int o = tid; o < m * nv; o += kT) {
+    const int a = o % m, v = o / m;
+    A sa = 0;
+    for (int gg = 0; gg < G; ++gg) sa += red[(v * G + gg) * m + a];
+    double s = (double)sa;
+    if (mode == MODE_STORE) {
+      out[R.out_off + a + R.out_ld * v] = s;
+    } else if (mode == MODE_ACCUM) {
+      out[R.out_off + a + R.out_ld * v] += s;
+    } else {
+      const int64_t i = R.out_off + a;
+      s += ep.zn[i + ep.n * v];
+      double* y = ep.Y + ep.perm[i] + ep.ldy * v;
+      *y = ep.beta == 0.0 ? ep.alpha * s : ep.alpha * s + ep.beta * *y;
     }
   }
 }
 
-// Transposed block-column product (op 'T'): out[b, v] = sum over the blocks
-// of the column, sum_a Mblk[a, b] in[a, v].  Column b of a stored block is
-// contiguous, so each thread streams its own column.
-__global__ void k_gather_rows(const RowDesc* __restrict__ rows, const int64_t* __restrict__ bdata,
-                              const int32_t* __restrict__ bmr, const int64_t* __restrict__ bin,
-                              const double* __restrict__ data, const double* __restrict__ in,
-                              double* __restrict__ out, int nv) {
+// Rows with more blocks than the LDS tables hold: one thread per output row
+// and vector walks the columns (store mode only).
+__global__ __launch_bounds__(kT) void k_rows_wide(const RowDesc* __restrict__ rows,
+                                                  const int32_t* __restrict__ colend,
+                                                  const int64_t* __restrict__ in_off,
+                                                  const double* __restrict__ data, const double* in, double* out,
+                                                  int nv) {
+  const RowDesc R = rows[blockIdx.x];
+  const int m = R.nrows;
+  const int ncols = R.blk_end > R.blk_begin ? colend[R.blk_end - 1] : 0;
+  for (int o = threadIdx.x; o < m * nv; o += kT) {
+    const int a = o % m, v = o / m;
+    double s = 0.0;
+    int b = R.blk_begin, bstart = 0;
+    for (int j = 0; j < ncols; ++j) {
+      while (j >= colend[b]) bstart = colend[b++];
+      s += data[R.data_off + a + (int64_t)m * j] * in[in_off[b] + (j - bstart) + R.in_ld * v];
+    }
+    out[R.out_off + a + R.out_ld * v] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-vector path (FP64 MFMA).  Vector trees and the tree-ordered input and
+// dense partial are row-major with NVP = 16*NT vectors per row (padding
+// vectors are zero).  The same row lists as the streaming kernel are used:
+// out (m x NVP) = M (m x ncols, column-major) * B (ncols x NVP, gathered).
+// v_mfma_f64_16x16x4f64 lane layout (wave64): A[i][k] at lane i + 16k,
+// B[k][j] at lane j + 16k, and the 4 accumulator doubles of lane l hold
+// C[4*(l/16) + r][l%16], r = 0..3.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// X~ (tree order, row-major NVP) from X (original order, column-major):
+// thread per original index j reads X[j, v] (coalesced over j) and writes
+// the row of tree position pinv[j].
+__global__ void k_permute_in_rm(const double* __restrict__ X, int64_t ldx, const int32_t* __restrict__ pinv,
+                                double* __restrict__ xt, int64_t n, int nv, int nvp) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double* row = xt + (int64_t)pinv[j] * nvp;
+  for (int v = 0; v < nvp; ++v) row[v] = v < nv ? X[j + ldx * v] : 0.0;
+}
+
+// Y[j, v] = alpha * Z[pinv[j], v] + beta * Y[j, v] (Z row-major NVP, tree order).
+__global__ void k_permute_out_rm(const double* __restrict__ Z, const int32_t* __restrict__ pinv, double alpha,
+                                 double beta, double* __restrict__ Y, int64_t ldy, int64_t n, int nv, int nvp) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double* row = Z + (int64_t)pinv[j] * nvp;
+  for (int v = 0; v < nv; ++v) {
+    double* y = Y + j + ldy * v;
+    *y = beta == 0.0 ? alpha * row[v] : alpha * row[v] + beta * *y;
+  }
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<double> { typedef d4 t; };
+template <> struct MfmaAcc<float> { typedef f4 t; };
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// T = double: FP64 MFMA; T = float: FP32 MFMA on the FP32 copy of the
+// low-rank data (inputs rounded to FP32 when staged, FP32 accumulation).
+// Rows are taken grid-stride (row = blockIdx.x, blockIdx.x + gridDim.x, ...):
+// with one workgroup per row this is a plain launch, with fewer workgroups
+// it is a persistent kernel.  KC is the number of columns staged per LDS
+// chunk (KC/4 MFMA k-steps).
+template <typename T, int NT, int MAXT, int KC>
+__global__ __launch_bounds__(kT) void k_rows_mfma(const RowDesc* __restrict__ rows, int64_t nrows,
+                                                  const int32_t* __restrict__ colend,
+                                                  const int64_t* __restrict__ in_off,
+                                                  const T* __restrict__ data, const double* in, double* out,
+                                                  int mode) {
+  typedef typename MfmaAcc<T>::t CT;
+  constexpr int NVP = 16 * NT;
+  __shared__ T bs[KC * NVP];
+  __shared__ int32_t s_end[kNbMax];
+  __shared__ int64_t s_in[kNbMax];
+  __shared__ int64_t s_src[KC];  // input row of each column of the chunk
+  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+  __syncthreads();  // LDS of the previous row fully consumed
+  const RowDesc R = rows[ri];
+  const int m = R.nrows;
+  if (m <= 0) continue;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = R.blk_end - R.blk_begin;
+  for (int i = tid; i < nb; i += kT) {
+    s_end[i] = colend[R.blk_begin + i];
+    s_in[i] = in_off[R.blk_begin + i];
+  }
+  __syncthreads();
+  const int ncols = nb > 0 ? s_end[nb - 1] : 0;
+  const int mt = (m + 15) >> 4;  // 16-row tiles of M; waves take tiles w, w+4, ... (at most MAXT each)
+  CT acc[MAXT][NT];
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = CT{0, 0, 0, 0};
+  const int arow = lane & 15, akk = lane >> 4;  // A fragment: row within tile, k within step
+  const T* M = data + R.data_off;
+
+  for (int c0 = 0; c0 < ncols; c0 += KC) {
+    const int cn = min(KC, ncols - c0);
+    if (c0 > 0) __syncthreads();
+    if (tid < cn) {
+      const int col = c0 + tid;
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[mid] > col) hi = mid; else lo = mid + 1;
+      }
+      s_src[tid] = s_in[lo] + (col - (lo > 0 ? s_end[lo - 1] : 0));
+    }
+    __syncthreads();
+    for (int e = tid; e < KC * NVP; e += kT) {
+      const int j = e / NVP, v = e - j * NVP;
+      bs[e] = j < cn ? (T)in[s_src[j] * NVP + v] : (T)0;
+    }
+    __syncthreads();
+    const int nsteps = (cn + 3) >> 2;
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int tile = wave + 4 * ti;
+      if (tile >= mt) break;
+      const int r = tile * 16 + arow;
+      const bool rok = r < m;
+      const T* Ar = M + r + (int64_t)m * c0;
+      int s = 0;
+      for (; s + 3 < nsteps; s += 4) {
+        T a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int col = 4 * (s + u) + akk;
+          a[u] = (rok && col < cn) ? __builtin_nontemporal_load(Ar + (int64_t)m * col) : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const T b = bs[(4 * (s + u) + akk) * NVP + 16 * j + arow];
+            acc[ti][j] = mfma16x16x4(a[u], b, acc[ti][j]);
+          }
+      }
+      for (; s < nsteps; ++s) {
+        const int col = 4 * s + akk;
+        const T a = (rok && col < cn) ? __builtin_nontemporal_load(Ar + (int64_t)m * col) : (T)0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const T b = bs[(4 * s + akk) * NVP + 16 * j + arow];
+          acc[ti][j] = mfma16x16x4(a, b, acc[ti][j]);
+        }
+      }
+    }
+  }
+  // epilogue: lane holds C[4*(lane/16) + r][lane%16] of each of its tiles
+#pragma unroll
+  for (int ti = 0; ti < MAXT; ++ti) {
+    const int tile = wave + 4 * ti;
+    if (tile >= mt) break;
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = tile * 16 + 4 * akk + r;
+        if (a < m) {
+          double* o = out + (R.out_off + a) * NVP + 16 * j + arow;
+          if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
+          else *o += (double)acc[ti][j][r];
+        }
+      }
+  }
+  }  // rows
+}
+
+// Transposed block-column product (op 'T') for the coupling and dense
+// phases: out[b, v] = sum over the blocks of the column, sum_a Mblk[a, b]
+// x_blk[a, v].  Each stored block (mr x ms, column-major, contiguous) is
+// copied into LDS with coalesced loads, its input segment too, then thread
+// (b, q) sums rows a = q, q+Q, ... of column b; column b sits at LDS offset
+// b*(mr+1) so that neighbouring lanes hit different banks.  Partials over q
+// are combined in a fixed order: deterministic, no atomics.
+template <typename T, int NVB>
+__global__ __launch_bounds__(kT) void k_rows_t(const RowDesc* __restrict__ rows, const int64_t* __restrict__ bdata,
+                                               const int32_t* __restrict__ bmr, const int64_t* __restrict__ bin,
+                                               const T* __restrict__ data, const double* in, double* out,
+                                               int nv) {
+  typedef typename Acc<T>::t A;
+  constexpr int LDSD = 4352;  // elements: a 64 x 64 block with padding (64*65 = 4160) and slack
+  __shared__ A blk[LDSD];
+  __shared__ A xs[NVB * kMaxDim];
   const RowDesc R = rows[blockIdx.x];
   const int ms = R.nrows;
-  for (int o = threadIdx.x; o < ms * nv; o += blockDim.x) {
-    const int b = o % ms, v = o / ms;
-    double s = 0.0;
-    for (int blk = R.blk_begin; blk < R.blk_end; ++blk) {
-      const int mr = bmr[blk];
-      const double* col = data + bdata[blk] + (int64_t)mr * b;
-      const double* x = in + bin[blk] + R.in_ld * v;
-      for (int a = 0; a < mr; ++a) s += col[a] * x[a];
+  if (ms <= 0) return;
+  const int tid = threadIdx.x;
+  const int Q = kT / ms;
+  const int b = tid % ms, q = tid / ms;
+  A acc[NVB];
+#pragma unroll
+  for (int v = 0; v < NVB; ++v) acc[v] = 0;
+  for (int k = R.blk_begin; k < R.blk_end; ++k) {
+    const int mr = bmr[k];
+    const T* M = data + bdata[k];
+    const double* x = in + bin[k];
+    // rows handled per LDS pass, so that (rows+1)*ms fits
+    const int rows_per = min(mr, LDSD / ms - 1);
+    for (int a0 = 0; a0 < mr; a0 += rows_per) {
+      const int ra = min(rows_per, mr - a0);
+      __syncthreads();  // previous pass consumed
+      for (int e = tid; e < ra * ms; e += kT) {
+        const int cb = e / ra, ca = e - cb * ra;
+        blk[cb * (ra + 1) + ca] = __builtin_nontemporal_load(M + a0 + ca + (int64_t)mr * cb);
+      }
+      for (int e = tid; e < ra * NVB; e += kT) {
+        const int v = e / ra, a = e - v * ra;
+        xs[v * kMaxDim + a] = v < nv ? (A)x[a0 + a + R.in_ld * v] : (A)0;
+      }
+      __syncthreads();
+      if (q < Q) {
+        const A* col = blk + b * (ra + 1);
+        for (int a = q; a < ra; a += Q) {
+          const A mv = col[a];
+#pragma unroll
+          for (int v = 0; v < NVB; ++v) acc[v] = __builtin_fma(mv, xs[v * kMaxDim + a], acc[v]);
+        }
+      }
     }
-    out[R.out_off + b + R.out_ld * v] = s;
+  }
+  __syncthreads();
+  A* red = blk;  // Q*ms <= kT, so NVB*Q*ms <= LDSD for NVB <= 16
+  if (q < Q) {
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) red[(v * Q + q) * ms + b] = acc[v];
+  }
+  __syncthreads();
+  for (int o = tid; o < ms * nv; o += kT) {
+    const int bb = o % ms, v = o / ms;
+    A s = 0;
+    for (int qq = 0; qq < Q; ++qq) s += red[(v * Q + qq) * ms + bb];
+    out[R.out_off + bb + R.out_ld * v] = (double)s;
   }
 }
 
@@ -204,67 +450,150 @@ hipError_t launch_scale(double* Y, int64_t ldy, int64_t n, int64_t nv, double be
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_up(const double* B, int k, int64_t leaf0, int64_t nleaves, const int32_t* lo,
-                          const int32_t* m, const int64_t* hoff, const double* xt, int64_t n, double* xh,
-                          int64_t H, int nv, hipStream_t s) {
-  if (nleaves == 0 || k == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_up, dim3((unsigned)nleaves), dim3(kSmallThreads), 0, s, B, k, leaf0, lo, m, hoff,
-                     xt, n, xh, H, nv);
-  return hipGetLastError();
-}
-
-hipError_t launch_transfer_up(const double* T, int kc, int kp, int64_t pbegin, int64_t pcount, int64_t cbegin,
-                              const int32_t* cptr, const int64_t* hoff, double* xh, int64_t H, int nv,
-                              hipStream_t s) {
-  if (pcount == 0 || kp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transfer_up, dim3((unsigned)pcount), dim3(kSmallThreads), 0, s, T, kc, kp, pbegin,
-                     cbegin, cptr, hoff, xh, H, nv);
-  return hipGetLastError();
-}
-
-hipError_t launch_transfer_down(const double* T, int kc, int kp, int64_t cbegin, int64_t ccount,
-                                const int32_t* parent, const int64_t* hoff, double* yh, int64_t H, int nv,
-                                hipStream_t s) {
-  if (ccount == 0 || kc == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transfer_down, dim3((unsigned)ccount), dim3(kSmallThreads), 0, s, T, kc, kp, cbegin,
-                     parent, hoff, yh, H, nv);
-  return hipGetLastError();
-}
-
-hipError_t launch_leaf_down(const double* B, int k, int64_t leaf0, int64_t nleaves, const int32_t* lo,
-                            const int32_t* m, const int64_t* hoff, const double* yh, int64_t H, const double* zn,
-                            int64_t n, const int32_t* perm, double alpha, double beta, double* Y, int64_t ldy,
-                            int nv, hipStream_t s) {
-  if (nleaves == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_down, dim3((unsigned)nleaves), dim3(kSmallThreads), 0, s, B, k, leaf0, lo, m, hoff,
-                     yh, H, zn, n, perm, alpha, beta, Y, ldy, nv);
-  return hipGetLastError();
-}
-
-hipError_t launch_stream_rows(const StreamSched& sc, const double* data, const double* in, double* out, int nv,
-                              hipStream_t s) {
-  const size_t nrows = sc.rows.size();
+template <typename T>
+hipError_t launch_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                       const T* data, const double* in, double* out, int nv, int mode, const Epilogue& ep,
+                       hipStream_t s) {
   if (nrows == 0) return hipSuccess;
-  if (nv <= 1) {
-    hipLaunchKernelGGL(k_stream_rows<1>, dim3((unsigned)nrows), dim3(kRowThreads), 0, s, sc.d_rows, sc.d_colend,
-                       sc.d_in_off, data, in, out, nv);
-  } else if (nv <= 4) {
-    hipLaunchKernelGGL(k_stream_rows<4>, dim3((unsigned)nrows), dim3(kRowThreads), 0, s, sc.d_rows, sc.d_colend,
-                       sc.d_in_off, data, in, out, nv);
-  } else {
-    hipLaunchKernelGGL(k_stream_rows<8>, dim3((unsigned)nrows), dim3(kRowThreads), 0, s, sc.d_rows, sc.d_colend,
-                       sc.d_in_off, data, in, out, nv);
+  const dim3 grid((unsigned)nrows), block(kT);
+  if (nv <= 1)
+    hipLaunchKernelGGL((k_rows<T, 1>), grid, block, 0, s, rows, colend, in_off, data, in, out, nv, mode, ep);
+  else if (nv == 2)
+    hipLaunchKernelGGL((k_rows<T, 2>), grid, block, 0, s, rows, colend, in_off, data, in, out, nv, mode, ep);
+  else if (nv <= 4)
+    hipLaunchKernelGGL((k_rows<T, 4>), grid, block, 0, s, rows, colend, in_off, data, in, out, nv, mode, ep);
+  else
+    return hipErrorInvalidValue;  // callers pass at most kPassVectors vectors
+  return hipGetLastError();
+}
+template hipError_t launch_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
+                                        const double*, double*, int, int, const Epilogue&, hipStream_t);
+template hipError_t launch_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
+                                       const double*, double*, int, int, const Epilogue&, hipStream_t);
+
+template <typename T>
+hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                            const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
+                            hipStream_t s, int kc, int64_t grid) {
+  if (nrows == 0) return hipSuccess;
+  const dim3 g((unsigned)(grid > 0 && grid < nrows ? grid : nrows)), block(kT);
+#define H2_MFMA3(NT, MAXT, KC) \
+  hipLaunchKernelGGL((k_rows_mfma<T, NT, MAXT, KC>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, mode)
+#define H2_MFMA(NT)                                     \
+  do {                                                  \
+    if (max_rows <= 64) {                               \
+      if (kc == 32) H2_MFMA3(NT, 1, 32);                \
+      else H2_MFMA3(NT, 1, 64);                         \
+    } else {                                            \
+      if (kc == 32) H2_MFMA3(NT, 4, 32);                \
+      else H2_MFMA3(NT, 4, 64);                         \
+    }                                                   \
+  } while (0)
+  switch (nvp) {
+    case 16: H2_MFMA(1); break;
+    case 32: H2_MFMA(2); break;
+    case 48: H2_MFMA(3); break;
+    case 64: H2_MFMA(4); break;
+    default: return hipErrorInvalidValue;
   }
+#undef H2_MFMA
+#undef H2_MFMA3
+  return hipGetLastError();
+}
+template hipError_t launch_rows_mfma<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
+                                             const double*, double*, int, int, int, hipStream_t, int, int64_t);
+template hipError_t launch_rows_mfma<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
+                                            const double*, double*, int, int, int, hipStream_t, int, int64_t);
+
+// Batched input permutation: operator blockIdx.y, original index j.  Rows
+// of the workspace arena are row-major with nvp vectors; padding vectors,
+// operators with nv == 0 and alpha == 0 get zeros (X is then not read).
+__global__ void k_batch_permute_in(const BatchItem* __restrict__ items, const int32_t* __restrict__ pinv,
+                                   double* __restrict__ ws, int nvp) {
+  const BatchItem it = items[blockIdx.y];
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= it.n) return;
+  double* row = ws + (it.xt_row + pinv[it.pinv_off + j]) * nvp;
+  const bool use = it.nv > 0 && it.alpha != 0.0;
+  for (int v = 0; v < nvp; ++v) row[v] = (use && v < it.nv) ? it.X[j + it.ldx * v] : 0.0;
+}
+
+// Y_i[j, v] = alpha_i * Z_i[pinv_i[j], v] + beta_i * Y_i[j, v], v < nv_i.
+__global__ void k_batch_permute_out(const BatchItem* __restrict__ items, const int32_t* __restrict__ pinv,
+                                    const double* __restrict__ ws, int nvp) {
+  const BatchItem it = items[blockIdx.y];
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= it.n) return;
+  const double* row = ws + (it.zn_row + pinv[it.pinv_off + j]) * nvp;
+  for (int v = 0; v < it.nv; ++v) {
+    double* y = it.Y + j + it.ldy * v;
+    const double z = it.alpha == 0.0 ? 0.0 : it.alpha * row[v];
+    *y = it.beta == 0.0 ? z : z + it.beta * *y;
+  }
+}
+
+hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t nmax, const int32_t* pinv,
+                                double* ws, int nvp, bool out, hipStream_t s) {
+  if (count == 0 || nmax == 0) return hipSuccess;
+  const dim3 grid(grid1d(nmax, 256), (unsigned)count);
+  if (out) hipLaunchKernelGGL(k_batch_permute_out, grid, dim3(256), 0, s, items, pinv, ws, nvp);
+  else hipLaunchKernelGGL(k_batch_permute_in, grid, dim3(256), 0, s, items, pinv, ws, nvp);
   return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(const GatherSched& sc, const double* data, const double* in, double* out, int nv,
-                              hipStream_t s) {
-  const size_t nrows = sc.rows.size();
-  if (nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)nrows), dim3(kRowThreads), 0, s, sc.d_rows, sc.d_data, sc.d_mr,
-                     sc.d_in_off, data, in, out, nv);
+// Reduced-precision copy of FP64 data (round to nearest).
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
+
+hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pinv, double* xt, int64_t n, int nv,
+                                int nvp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_in_rm, dim3(grid1d(n, 256)), dim3(256), 0, s, X, ldx, pinv, xt, n, nv, nvp);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double alpha, double beta, double* Y,
+                                 int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_out_rm, dim3(grid1d(n, 256)), dim3(256), 0, s, Z, pinv, alpha, beta, Y, ldy, n, nv,
+                     nvp);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_wide(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                            const double* data, const double* in, double* out, int nv, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_wide, dim3((unsigned)nrows), dim3(kT), 0, s, rows, colend, in_off, data, in, out, nv);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(const RowDesc* rows, int64_t nrows, const int64_t* bdata, const int32_t* bmr,
+                         const int64_t* bin, const T* data, const double* in, double* out, int nv,
+                         hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  const dim3 grid((unsigned)nrows), block(kT);
+  if (nv <= 1)
+    hipLaunchKernelGGL((k_rows_t<T, 1>), grid, block, 0, s, rows, bdata, bmr, bin, data, in, out, nv);
+  else if (nv == 2)
+    hipLaunchKernelGGL((k_rows_t<T, 2>), grid, block, 0, s, rows, bdata, bmr, bin, data, in, out, nv);
+  else if (nv <= 4)
+    hipLaunchKernelGGL((k_rows_t<T, 4>), grid, block, 0, s, rows, bdata, bmr, bin, data, in, out, nv);
+  else
+    return hipErrorInvalidValue;  // callers pass at most kPassVectors vectors
+  return hipGetLastError();
+}
+template hipError_t launch_gather<double>(const RowDesc*, int64_t, const int64_t*, const int32_t*, const int64_t*,
+                                          const double*, const double*, double*, int, hipStream_t);
+template hipError_t launch_gather<float>(const RowDesc*, int64_t, const int64_t*, const int32_t*, const int64_t*,
+                                         const float*, const double*, double*, int, hipStream_t);
 
 }  // namespace h2

@@ -102,13 +102,15 @@ def test_float_representations(seed):
     g.close()
 
 
+@pytest.mark.parametrize("nv", [3, 20])
 @pytest.mark.parametrize("kind,dim,p", [("laplace", 3, 3), ("exp", 2, 6), ("gauss", 2, 5)])
-def test_built_operators(kind, dim, p):
+def test_built_operators(kind, dim, p, nv):
+    """Odd ranks and leaf sizes (27, 47): exercises the masked MFMA tiles."""
     P = h2gen.points(6000, dim, 5 + dim)
     buf = h2gen.build(P, leaf=48, p=p, eta=0.7, kernel=kind, param=0.15)
     ref = oracle.Oracle(buf.array)
     g = operator(buf.array)
-    X = h2gen.vectors(6000, 3, 9)
+    X = h2gen.vectors(6000, nv, 9)
     for op in "NT":
         want = ref.gemv(X, op=op)
         got = run(g, X, op)

@@ -1,0 +1,65 @@
+"""The reduced-precision path (FP32 low-rank phases, FP64 dense near field and
+final update) against the FP64 oracle.
+
+Integer representations: every partial sum is an integer below 2^24, so the
+FP32 path must be bit-exact too (this pins its indexing independently of
+rounding).  Floating-point workloads: the low-rank data and arithmetic are
+rounded to FP32 (unit roundoff 2^-24 ~ 6e-8); the elementwise bar is
+2e-5 * B (B = oracle product in absolute values, which bounds every partial
+sum), i.e. about 300 FP32 unit roundoffs, and the normwise relative error
+is reported by the benchmark."""
+import numpy as np
+import pytest
+
+import h2gen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL32 = 2e-5
+
+
+def run(g, X, op="N", alpha=1.0, beta=0.0, Y0=None, precision="fp32"):
+    Xd = torch.from_numpy(np.asfortranarray(X)).cuda()
+    Yd = None if Y0 is None else torch.from_numpy(np.asfortranarray(Y0)).cuda()
+    Y = g.gemv(Xd, op=op, alpha=alpha, beta=beta, Y=Yd, precision=precision)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", [dict(q=2), dict(q=3, separate=True), dict(q=3, max_children=1),
+                                  dict(q=0), dict(q=4, max_children=2, p_adm=0.3)])
+def test_fp32_integer_bitwise(case):
+    from paper_2109_05451_amd import H2Operator
+    for seed in range(3):
+        buf = h2gen.random_rep(3000 + seed, **case)
+        ref = oracle.Oracle(buf)
+        g = H2Operator(buf)
+        g.prepare("fp32")
+        rng = np.random.default_rng(seed)
+        for nv in (1, 4, 17):
+            X = rng.integers(-2, 3, size=(g.n, nv)).astype(np.float64)
+            Y0 = rng.integers(-2, 3, size=(g.n, nv)).astype(np.float64)
+            for op in "NT":
+                want = ref.gemv(X, op=op, alpha=2.0, beta=-1.0, Y=Y0)
+                got = run(g, X, op, 2.0, -1.0, Y0)
+                assert np.array_equal(got, want), (case, seed, nv, op)
+        g.close()
+
+
+@pytest.mark.parametrize("nv", [1, 3, 16, 40])
+def test_fp32_small_config(nv):
+    from paper_2109_05451_amd import H2Operator
+    buf = h2gen.build_config("c1_2d_4096")
+    ref = oracle.Oracle(buf.array)
+    g = H2Operator(buf.array)
+    X = h2gen.vectors(4096, nv, 2001)
+    for op in "NT":
+        want = ref.gemv(X, op=op)
+        B = ref.gemv(X, op=op, absval=True)
+        got = run(g, X, op)
+        assert np.all(np.abs(got - want) <= TOL32 * B), np.max(np.abs(got - want) / B)
+        rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+        assert 0 < rel < 1e-5, rel  # really reduced precision, and close
+    g.close()
