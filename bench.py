@@ -92,6 +92,169 @@ def cpu_baseline(buf, X, budget_s=30.0):
     return float(np.mean(times)), len(times), oracle.threads()
 
 
+def batch_ops(count=256, seed0=3000):
+    """The batched workload: count independent 2D operators, N = round(2^U(12,16)),
+    leaf U{32..64}, Chebyshev p in {4,5,6} (rank 16-36), exp(-r/l) with
+    l ~ U[0.05, 0.2], eta 0.7; nv ~ U{1..32}.  Operator i: points seed
+    seed0+i, vectors seed 4000+i."""
+    import h2gen
+    specs = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        n = int(round(2 ** rng.uniform(12, 16)))
+        leaf = int(rng.integers(32, 65))
+        p = int(rng.choice([4, 5, 6]))
+        ell = float(rng.uniform(0.05, 0.2))
+        nv = int(rng.integers(1, 33))
+        specs.append(dict(n=n, leaf=leaf, p=p, ell=ell, nv=nv, seed_pts=seed0 + i, seed_vec=4000 + i))
+    return specs
+
+
+def stored_entries(buf) -> int:
+    """Stored entries of every part, the column basis counted even when shared."""
+    from h2gen import fmt
+    r = fmt.parse(buf)
+    return int(r["U"].size + r["V"].size + r["E"].size + r["F"].size + r["S"].size + r["D"].size)
+
+
+def bench_batch(args, torch):
+    import h2gen
+    from paper_2109_05451_amd import H2Batch
+    specs = batch_ops(args.batch_count)
+    t0 = time.perf_counter()
+    bufs, flops = [], 0.0
+    for sp in specs:
+        b = h2gen.build(h2gen.points(sp["n"], 2, sp["seed_pts"]), sp["leaf"], sp["p"], 0.7, "exp", sp["ell"])
+        flops += 2.0 * sp["nv"] * stored_entries(b.array) + sp["n"] * sp["nv"]
+        bufs.append(b)
+    print(f"# built {len(bufs)} operators in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    batch = H2Batch([b.array for b in bufs], nv_max=32)
+    info = batch.info()
+    for b in bufs:
+        b.free()
+    print(f"# batch loaded in {time.perf_counter() - t0:.1f} s: {info}", file=sys.stderr, flush=True)
+    Xs = [torch.from_numpy(np.asfortranarray(h2gen.vectors(sp["n"], sp["nv"], sp["seed_vec"]))).cuda() for sp in specs]
+    Ys = [torch.empty((sp["nv"], sp["n"]), dtype=torch.float64, device="cuda").t() for sp in specs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.tune(Xs, Ys)
+    torch.cuda.synchronize()
+    print(f"# tuned in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    batch.graph(True)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            batch.gemv(Xs, Ys, stream=stream)
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(stream)
+            batch.gemv(Xs, Ys, stream=stream)
+            b.record(stream)
+        stream.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in ev])
+    srt = np.sort(per)
+    t_ms = float(np.mean(srt[1:-1] if srt.size > 2 else srt))
+    batch.close()
+    return {"metric": "H2 matvec Gflop/s (batched operators)", "value": round(flops / (t_ms * 1e-3) / 1e9, 2),
+            "unit": "Gflop/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(t_ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{len(specs)} independent 2D operators, N=round(2^U(12,16)), leaf U{{32..64}}, "
+                                   "Chebyshev p in {4,5,6}, exp(-r/l) l~U[0.05,0.2], eta 0.7, nv~U{1..32}; "
+                                   "merged level by level into single launches, autotuned, HIP graph replay",
+                       "operators": len(specs), "total_n": info["total_n"], "launches_per_call": info["launches"],
+                       "flops_per_call": flops},
+            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
+                           "p99": round(float(np.percentile(per, 99)), 4)}}
+
+
+def bench_serving(args, torch):
+    """8 resident operators (4 of the 4096-point 2D shape, 4 of the 2^20-point
+    2D shape), Poisson arrivals at about 70% of the measured capacity, nv
+    uniform in {1, 4, 16, 64}, half FP64 and half FP32, continuous batching."""
+    import threading
+    import h2gen
+    from paper_2109_05451_amd import H2Operator, H2Server
+    ops, flops_pv = [], []
+    for i in range(8):
+        name = "c1_2d_4096" if i < 4 else "c2_2d_1m"
+        cfg = h2gen.CONFIGS[name]
+        b = h2gen.build(h2gen.points(cfg["n"], 2, 5100 + i), cfg["leaf"], cfg["p"], cfg["eta"], cfg["kernel"],
+                        cfg["param"])
+        flops_pv.append(2.0 * stored_entries(b.array) + cfg["n"])
+        ops.append(H2Operator(b.array))
+        b.free()
+    print("# operators resident", file=sys.stderr, flush=True)
+    for o in ops:
+        o.prepare("fp32")
+    rng = np.random.default_rng(5000)
+    nvs = [1, 4, 16, 64]
+    pool = {(i, v): torch.randn(v, ops[i].n, dtype=torch.float64, device="cuda").t() for i in range(8) for v in nvs}
+    server = H2Server(ops, slots=4, budget_bytes=8 << 30, max_fuse_nv=64)
+    torch.cuda.synchronize()
+
+    def draw():
+        i = int(rng.integers(0, 8))
+        v = int(rng.choice(nvs))
+        return i, v, ("fp64" if rng.random() < 0.5 else "fp32")
+
+    # capacity: a closed burst
+    burst = [draw() for _ in range(200)]
+    t0 = time.perf_counter()
+    ids = [server.submit(i, pool[(i, v)], p) for i, v, p in burst]
+    for r in ids:
+        server.wait(r)
+    cap = len(burst) / (time.perf_counter() - t0)
+    rate = 0.7 * cap
+    print(f"# capacity {cap:.1f} req/s; offered load {rate:.1f} req/s", file=sys.stderr, flush=True)
+    reqs = [draw() for _ in range(args.serve_requests)]
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    ids = [None] * len(reqs)
+
+    def submitter():
+        t_next = time.perf_counter()
+        for k, (i, v, p) in enumerate(reqs):
+            t_next += gaps[k]
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids[k] = server.submit(i, pool[(i, v)], p)
+
+    st0 = server.stats()
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = []
+    for k in range(len(reqs)):
+        while ids[k] is None:
+            time.sleep(1e-4)
+        _, ms = server.wait(ids[k])
+        lat.append(ms)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = server.stats()
+    served_flops = sum(flops_pv[i] * v for i, v, _ in reqs)
+    server.close()
+    for o in ops:
+        o.close()
+    lat = np.array(lat)
+    return {"metric": "H2 matvec serving throughput", "value": round(len(reqs) / wall, 2), "unit": "requests/s",
+            "n_gpus": 1, "steps": len(reqs), "warmup": len(burst), "ms_per_step": round(1e3 * wall / len(reqs), 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+            "config": {"workload": "8 resident operators (4 x 2D N=4096 k=16, 4 x 2D N=2^20 k=36, exp(-r/0.1), "
+                                   "eta 0.7); Poisson arrivals at 70% of measured capacity; nv in {1,4,16,64}; "
+                                   "50/50 FP64/FP32; continuous batching over 4 slots",
+                       "offered_rate": round(rate, 2), "capacity": round(cap, 2)},
+            "gflops": round(served_flops / wall / 1e9, 2),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3), "mean": round(float(lat.mean()), 3)},
+            "server": {"calls": st["calls"] - st0["calls"], "requests": st["completed"] - st0["completed"],
+                       "vectors_per_call": round((st["vectors"] - st0["vectors"]) / max(1, st["calls"] - st0["calls"]), 2),
+                       "max_inflight_calls": st["max_inflight_calls"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +264,8 @@ def main():
     ap.add_argument("--nv", type=int, default=None, help="vectors of the headline run (default: config's first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256, help="operators of the batched workload")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -118,6 +283,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
+        return
+    if args.config == "c4_batch":
+        print(json.dumps(bench_batch(args, torch)), flush=True)
+        return
+    if args.config == "c5_serving":
+        print(json.dumps(bench_serving(args, torch)), flush=True)
         return
     import h2gen
     from paper_2109_05451_amd import H2Operator

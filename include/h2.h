@@ -51,7 +51,9 @@ enum {
  * and the final Y update always run in FP64. */
 enum {
   H2_PREC_FP64 = 0, /* everything in FP64 */
-  H2_PREC_FP32 = 1  /* low-rank data stored and multiplied in FP32, FP32 accumulation */
+  H2_PREC_FP32 = 1, /* low-rank data stored and multiplied in FP32, FP32 accumulation */
+  H2_PREC_BF16 = 2  /* low-rank data in BF16 on the BF16 matrix cores, FP32 accumulation;
+                       op 'N' only (vectors are padded to multiples of 16) */
 };
 
 /* Structure and algorithmic work of a loaded operator.  "entries" count the
@@ -131,8 +133,10 @@ int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, in
  * The reduced-precision copy of the low-rank data is made on the device by
  * h2_prepare, or by the first call that needs it (device allocation).  The
  * result differs from the FP64 product by the rounding of the low-rank data
- * and arithmetic to that precision (about 1e-7 relative for FP32).
- * Errors: as h2_gemv, plus H2_EINVAL for an unknown precision. */
+ * and arithmetic to that precision (about 1e-7 relative for FP32, 1e-3 for
+ * BF16 data with FP32 accumulation).
+ * Errors: as h2_gemv, plus H2_EINVAL for an unknown precision and
+ * H2_EUNSUPPORTED for BF16 with op 'T'. */
 int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
                double beta, double* Y, int64_t ldy, int prec, void* stream);
 
@@ -218,6 +222,50 @@ int h2_batch_info(h2_batch b, int64_t* count, int64_t* total_n, double* flops_pe
 
 /* Release the batch (synchronizes the device first); NULL is a no-op. */
 int h2_batch_free(h2_batch b);
+
+/* ---- Serving loop -------------------------------------------------------
+ * A server keeps several loaded operators resident and serves matvec
+ * requests on them.  A scheduler thread admits work while a slot (a stream
+ * with its own workspace) is free and the device-memory budget has room for
+ * the call's input/output buffers; requests waiting for the same operator and
+ * precision are fused into one multi-vector product (up to max_fuse_nv
+ * vectors), so requests arriving while others run join the next call
+ * (continuous batching) and calls on different slots overlap on the GPU.
+ * Requests hold device pointers (column-major n x nv, leading dimension n,
+ * original point order) that must stay valid until the request completes. */
+typedef struct h2_server_s* h2_server;
+
+typedef struct {
+  int64_t submitted, completed;   /* requests */
+  int64_t calls;                  /* fused products issued */
+  int64_t vectors;                /* vectors served */
+  int64_t max_inflight_calls;     /* largest number of calls running at once */
+  int64_t slots;                  /* slots the budget allowed */
+  int64_t budget_bytes;           /* device memory for call buffers */
+} h2_server_stats_t;
+
+/* Create a server over `nops` loaded handles (all on one device; the server
+ * does not own them).  `slots` concurrent calls at most, each slot with a
+ * workspace sized for the largest operator; `budget_bytes` of device memory
+ * for the calls' fused input/output buffers (admission waits when it is
+ * exhausted); `max_fuse_nv` (1..64) vectors per fused call.
+ * Errors: H2_EINVAL, H2_ENOMEM, H2_EHIP. */
+int h2_server_create(const h2_handle* ops, int64_t nops, int64_t slots, int64_t budget_bytes,
+                     int64_t max_fuse_nv, h2_server* out);
+
+/* Queue Y <- op(A_op) X (op 'N', alpha 1, beta 0) in precision `prec`;
+ * nv <= max_fuse_nv.  Returns at once with the request id in *id. */
+int h2_server_submit(h2_server s, int64_t op, int prec, int64_t nv, const double* X, double* Y, int64_t* id);
+
+/* Block until request `id` has completed; *latency_ms (optional) receives
+ * the time from submission to completion as seen by the scheduler. */
+int h2_server_wait(h2_server s, int64_t id, double* latency_ms);
+
+/* Counters since creation. */
+int h2_server_stats(h2_server s, h2_server_stats_t* st);
+
+/* Finish all queued requests, stop the scheduler, release the server. */
+int h2_server_free(h2_server s);
 
 /* Message of the last error in the calling thread ("" if none).  The string
  * is owned by the library and valid until the next call in that thread. */

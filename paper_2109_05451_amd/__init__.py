@@ -21,9 +21,10 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve",
            "h2_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
-           "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_last_error")
+           "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
+           "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
 
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
 class H2Stats(ctypes.Structure):
@@ -47,6 +48,14 @@ class H2Profile(ctypes.Structure):
 class H2BatchItem(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64),
                 ("nv", ctypes.c_int64), ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
+class H2ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "submitted", "completed", "calls", "vectors", "max_inflight_calls", "slots", "budget_bytes")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class H2Error(RuntimeError):
@@ -103,6 +112,16 @@ def load_library(path: str = LIB_PATH):
     lib.h2_batch_info.restype = ci
     lib.h2_batch_free.argtypes = [vp]
     lib.h2_batch_free.restype = ci
+    lib.h2_server_create.argtypes = [ctypes.POINTER(vp), i64, i64, i64, i64, ctypes.POINTER(vp)]
+    lib.h2_server_create.restype = ci
+    lib.h2_server_submit.argtypes = [vp, i64, ci, i64, vp, vp, ctypes.POINTER(i64)]
+    lib.h2_server_submit.restype = ci
+    lib.h2_server_wait.argtypes = [vp, i64, ctypes.POINTER(dbl)]
+    lib.h2_server_wait.restype = ci
+    lib.h2_server_stats.argtypes = [vp, ctypes.POINTER(H2ServerStats)]
+    lib.h2_server_stats.restype = ci
+    lib.h2_server_free.argtypes = [vp]
+    lib.h2_server_free.restype = ci
     lib.h2_free.argtypes = [vp]
     lib.h2_free.restype = ci
     lib.h2_last_error.argtypes = []
@@ -282,4 +301,59 @@ class H2Batch:
         _check(load_library().h2_batch_graph(self._h, 1 if enable else 0))
 
 
-__all__ = ["H2Operator", "H2Batch", "H2Error", "load_library", "validate", "EXPORTS"]
+class H2Server:
+    """Serving loop over resident operators (continuous batching in C++).
+
+    ``submit(op, X, precision)`` queues Y = A_op X for a device tensor X
+    (n x nv, column-major, leading dimension n) and returns a request id; the
+    output tensor is allocated here and returned by ``wait(id)`` together with
+    the request's latency in ms."""
+
+    def __init__(self, ops, slots: int = 4, budget_bytes: int = 1 << 30, max_fuse_nv: int = 64):
+        lib = load_library()
+        self._ops = list(ops)
+        hs = (ctypes.c_void_p * len(self._ops))(*[o._h.value for o in self._ops])
+        h = ctypes.c_void_p()
+        _check(lib.h2_server_create(hs, len(self._ops), slots, budget_bytes, max_fuse_nv, ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit(self, op: int, X, precision: str = "fp64") -> int:
+        import torch
+        n = self._ops[op].n
+        X = X.reshape(n, -1) if X.dim() == 1 else X
+        if X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) != n):
+            X = X.t().contiguous().t()
+        nv = X.shape[1]
+        Y = torch.empty((nv, n), dtype=torch.float64, device=X.device).t()
+        rid = ctypes.c_int64()
+        _check(load_library().h2_server_submit(self._h, op, PRECISIONS[precision], nv, X.data_ptr(), Y.data_ptr(),
+                                               ctypes.byref(rid)))
+        self._live[rid.value] = (X, Y)
+        return rid.value
+
+    def wait(self, rid: int):
+        lat = ctypes.c_double()
+        _check(load_library().h2_server_wait(self._h, rid, ctypes.byref(lat)))
+        X, Y = self._live.pop(rid)
+        return Y, lat.value
+
+    def stats(self) -> dict:
+        st = H2ServerStats()
+        _check(load_library().h2_server_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().h2_server_free(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["H2Operator", "H2Batch", "H2Server", "H2Error", "load_library", "validate", "EXPORTS"]

@@ -105,19 +105,15 @@ void add_gather_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int in, int 
 void free_device(h2_op_s* h) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   F(h->d_mat); F(h->d_trans); F(h->d_perm); F(h->d_pinv); F(h->d_mat32); F(h->d_trans32);
+  F(h->d_mat16); F(h->d_trans16);
   F(h->rt.d_rows); F(h->rt.d_colend); F(h->rt.d_in_off);
   F(h->wide.d_rows); F(h->wide.d_colend); F(h->wide.d_in_off);
   F(h->gt.d_rows); F(h->gt.d_data); F(h->gt.d_mr); F(h->gt.d_in_off);
-  F(h->d_xt); F(h->d_xh); F(h->d_yh); F(h->d_zn);
   for (auto& set : h->ev_pool)
     for (hipEvent_t e : set)
       if (e) (void)hipEventDestroy(e);
   h->ev_pool.clear();
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-  if (h->side) (void)hipStreamDestroy(h->side);
-  h->ev_fork = h->ev_join = nullptr;
-  h->side = nullptr;
+  ws_destroy(&h->ws);
 }
 
 // Build plans and upload; the handle's device is current.
@@ -297,40 +293,21 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
       (rc = upload(h->gt.in_off, &h->gt.d_in_off, &ib)))
     return rc;
   h->index_bytes = ib;
-  HIP_TRY(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "hipStreamCreate");
-  HIP_TRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming), "hipEventCreate");
-  HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming), "hipEventCreate");
   h->stats.device_bytes = mat_bytes + ntrans * (int64_t)sizeof(double) + ib;
   return H2_OK;
 }
 
 int ensure_workspace(h2_op_s* h, int64_t nv) {
   const int64_t want = (nv > kPassVectors && h->mfma_ok) ? kPassVectorsMfma : kPassVectors;
-  if (h->cap >= want) return H2_OK;
-  const int64_t Hs = std::max<int64_t>(h->H, 1);
-  if (h->cap > 0) {  // grow: the old buffers may still be in use by queued work
+  if (h->ws.cap >= want) return H2_OK;
+  if (h->ws.cap > 0) {  // grow: the old buffers may still be in use by queued work
     HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(workspace growth)");
-    (void)hipFree(h->d_xt); (void)hipFree(h->d_xh); (void)hipFree(h->d_yh); (void)hipFree(h->d_zn);
-    h->d_xt = h->d_xh = h->d_yh = h->d_zn = nullptr;
-    h->stats.device_bytes -= (int64_t)sizeof(double) * (2 * h->n + 2 * Hs) * h->cap;
-    h->cap = 0;
+    h->stats.device_bytes -= ws_bytes(h->ws.n, h->ws.H, h->ws.cap);
+    ws_destroy(&h->ws);
   }
-  double *xt = nullptr, *xh = nullptr, *yh = nullptr, *zn = nullptr;
-  hipError_t e;
-  if ((e = hipMalloc(reinterpret_cast<void**>(&xt), sizeof(double) * h->n * want)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&xh), sizeof(double) * Hs * want)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&yh), sizeof(double) * Hs * want)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&zn), sizeof(double) * h->n * want)) != hipSuccess) {
-    if (xt) (void)hipFree(xt);
-    if (xh) (void)hipFree(xh);
-    if (yh) (void)hipFree(yh);
-    if (zn) (void)hipFree(zn);
-    return hip_fail(e, "hipMalloc(workspace)");
-  }
-  h->d_xt = xt; h->d_xh = xh; h->d_yh = yh; h->d_zn = zn;
-  h->stats.device_bytes += (int64_t)sizeof(double) * (2 * h->n + 2 * Hs) * want;
-  h->cap = want;
-  return H2_OK;
+  const int rc = ws_create(&h->ws, h->n, h->H, want);
+  if (rc == H2_OK) h->stats.device_bytes += ws_bytes(h->ws.n, h->ws.H, h->ws.cap);
+  return rc;
 }
 
 struct DeviceGuard {
@@ -375,10 +352,18 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out) {
 
 // nvp > 0: MFMA path with nvp vectors per row (row-major workspace).
 // f32: the low-rank launches read the FP32 copy (the dense phase never does).
-int run_launch(h2_op_s* h, const Launch& L, int nv, const Epilogue& ep, hipStream_t s, int nvp = 0,
-               int mode_override = -1, bool f32 = false) {
-  double* bufs[4] = {h->d_xt, h->d_xh, h->d_yh, h->d_zn};
-  const bool lowp = f32 && L.lowrank && L.kind != KIND_WIDE;
+int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Epilogue& ep, hipStream_t s,
+               int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64) {
+  double* bufs[4] = {w.xt, w.xh, w.yh, w.zn};
+  const bool lowp = prec == H2_PREC_FP32 && L.lowrank && L.kind != KIND_WIDE;
+  if (prec == H2_PREC_BF16 && L.lowrank && nvp > 0) {
+    const hipError_t eb = launch_rows_mfma_bf16(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend,
+                                                h->rt.d_in_off, L.arr == ARR_TRANS ? h->d_trans16 : h->d_mat16,
+                                                bufs[L.in], bufs[mode_override >= 0 ? BUF_ZN : L.out], nvp,
+                                                mode_override >= 0 ? mode_override : L.mode, L.max_rows, s);
+    if (eb != hipSuccess) return hip_fail(eb, "kernel launch");
+    return H2_OK;
+  }
   const double* data = L.arr == ARR_TRANS ? h->d_trans : h->d_mat;
   const float* data32 = L.arr == ARR_TRANS ? h->d_trans32 : h->d_mat32;
   double* out = bufs[mode_override >= 0 ? BUF_ZN : L.out];
@@ -427,13 +412,37 @@ int prepare_f32(h2_op_s* h) {
   return H2_OK;
 }
 
+int prepare_bf16(h2_op_s* h) {
+  if (h->d_mat16 || h->n_lowrank + h->n_trans == 0) return H2_OK;
+  void *m16 = nullptr, *t16 = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&m16, 2 * std::max<int64_t>(h->n_lowrank, 1))) != hipSuccess ||
+      (e = hipMalloc(&t16, 2 * std::max<int64_t>(h->n_trans, 1))) != hipSuccess) {
+    if (m16) (void)hipFree(m16);
+    return hip_fail(e, "hipMalloc(BF16 copy)");
+  }
+  h->d_mat16 = m16;
+  h->d_trans16 = t16;
+  const Plan& p = h->planN;
+  for (const auto* v : {&p.up, &p.couple, &p.down})
+    for (const Launch& L : *v)
+      HIP_TRY(launch_rows_to_bf16(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend,
+                                  L.arr == ARR_TRANS ? h->d_trans : h->d_mat, L.arr == ARR_TRANS ? t16 : m16, nullptr),
+              "BF16 copy");
+  HIP_TRY(launch_rows_to_bf16(h->rt.d_rows + p.out.row_begin, p.out.row_count, h->rt.d_colend, h->d_mat, m16, nullptr),
+          "BF16 copy");
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(BF16 copy)");
+  h->stats.device_bytes += 2 * (h->n_lowrank + h->n_trans);
+  return H2_OK;
+}
+
 // One pass of the product: nv <= kPassVectors vectors on the streaming path
 // (nvp == 0), or nv <= kPassVectorsMfma vectors padded to nvp on the MFMA path.
-int gemv_pass(h2_op_s* h, bool trans, double alpha, const double* X, int64_t ldx, int nv, double beta, double* Y,
-              int64_t ldy, hipStream_t s, int nvp, bool f32) {
+int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const double* X, int64_t ldx, int nv,
+              double beta, double* Y, int64_t ldy, hipStream_t s, int nvp, int prec) {
   const Plan& plan = trans ? h->planT : h->planN;
   std::array<hipEvent_t, 9>* ev = nullptr;
-  if (h->profiling) {
+  if (h->profiling && &w == &h->ws) {
     if (h->ev_used == h->ev_pool.size()) {
       std::array<hipEvent_t, 9> set{};
       for (auto& e : set) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
@@ -445,34 +454,34 @@ int gemv_pass(h2_op_s* h, bool trans, double alpha, const double* X, int64_t ldx
     if (ev) HIP_TRY(hipEventRecord((*ev)[i], st), "hipEventRecord");
     return H2_OK;
   };
-  Epilogue ep{h->d_zn, h->d_perm, alpha, beta, Y, ldy, h->n};
+  Epilogue ep{w.zn, h->d_perm, alpha, beta, Y, ldy, h->n};
   int rc;
 #define STEP(x) do { if ((rc = (x)) != H2_OK) return rc; } while (0)
   STEP(mark(0, s));
-  if (nvp) HIP_TRY(launch_permute_in_rm(X, ldx, h->d_pinv, h->d_xt, h->n, nv, nvp, s), "permute");
-  else HIP_TRY(launch_permute_in(X, ldx, h->d_perm, h->d_xt, h->n, nv, s), "permute");
+  if (nvp) HIP_TRY(launch_permute_in_rm(X, ldx, h->d_pinv, w.xt, h->n, nv, nvp, s), "permute");
+  else HIP_TRY(launch_permute_in(X, ldx, h->d_perm, w.xt, h->n, nv, s), "permute");
   STEP(mark(1, s));
   // dense near field on the side stream, concurrent with the low-rank phases
-  HIP_TRY(hipEventRecord(h->ev_fork, s), "hipEventRecord(fork)");
-  HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0), "hipStreamWaitEvent(fork)");
-  STEP(mark(5, h->side));
-  for (const Launch& L : plan.dense) STEP(run_launch(h, L, nv, ep, h->side, nvp));
-  STEP(mark(6, h->side));
-  HIP_TRY(hipEventRecord(h->ev_join, h->side), "hipEventRecord(join)");
-  for (const Launch& L : plan.up) STEP(run_launch(h, L, nv, ep, s, nvp, -1, f32));
+  HIP_TRY(hipEventRecord(w.ev_fork, s), "hipEventRecord(fork)");
+  HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");
+  STEP(mark(5, w.side));
+  for (const Launch& L : plan.dense) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
+  STEP(mark(6, w.side));
+  HIP_TRY(hipEventRecord(w.ev_join, w.side), "hipEventRecord(join)");
+  for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(2, s));
-  for (const Launch& L : plan.couple) STEP(run_launch(h, L, nv, ep, s, nvp, -1, f32));
+  for (const Launch& L : plan.couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(3, s));
-  for (const Launch& L : plan.down) STEP(run_launch(h, L, nv, ep, s, nvp, -1, f32));
+  for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(4, s));
-  HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0), "hipStreamWaitEvent(join)");
+  HIP_TRY(hipStreamWaitEvent(s, w.ev_join, 0), "hipStreamWaitEvent(join)");
   STEP(mark(7, s));
   if (nvp) {
     // Z += U y^ (into the dense partial), then Y = alpha Z[pinv] + beta Y
-    STEP(run_launch(h, plan.out, nv, ep, s, nvp, MODE_ACCUM, f32));
-    HIP_TRY(launch_permute_out_rm(h->d_zn, h->d_pinv, alpha, beta, Y, ldy, h->n, nv, nvp, s), "permute out");
+    STEP(run_launch(h, w, plan.out, nv, ep, s, nvp, MODE_ACCUM, prec));
+    HIP_TRY(launch_permute_out_rm(w.zn, h->d_pinv, alpha, beta, Y, ldy, h->n, nv, nvp, s), "permute out");
   } else {
-    STEP(run_launch(h, plan.out, nv, ep, s, 0, -1, f32));
+    STEP(run_launch(h, w, plan.out, nv, ep, s, 0, -1, prec));
   }
   STEP(mark(8, s));
 #undef STEP
@@ -527,12 +536,76 @@ int h2_reserve(h2_handle h, int64_t nv_max) {
   return ensure_workspace(h, nv_max);
 }
 
-int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double beta,
-               double* Y, int64_t ldy, int prec, void* stream) {
+}  // extern "C"
+
+namespace h2 {
+int64_t ws_bytes(int64_t n, int64_t H, int64_t cap) {
+  return (int64_t)sizeof(double) * (2 * std::max<int64_t>(n, 1) + 2 * std::max<int64_t>(H, 1)) * cap;
+}
+
+int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
+  *w = Workspace();
+  w->n = n;
+  w->H = H;
+  const int64_t nn = std::max<int64_t>(n, 1), Hs = std::max<int64_t>(H, 1);
+  hipError_t e;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&w->xt), sizeof(double) * nn * cap)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&w->xh), sizeof(double) * Hs * cap)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&w->yh), sizeof(double) * Hs * cap)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&w->zn), sizeof(double) * nn * cap)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming)) != hipSuccess) {
+    ws_destroy(w);
+    return hip_fail(e, "workspace allocation");
+  }
+  w->cap = cap;
+  return H2_OK;
+}
+
+void ws_destroy(Workspace* w) {
+  for (double* p : {w->xt, w->xh, w->yh, w->zn})
+    if (p) (void)hipFree(p);
+  if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
+  if (w->ev_join) (void)hipEventDestroy(w->ev_join);
+  if (w->side) (void)hipStreamDestroy(w->side);
+  *w = Workspace();
+}
+
+// The product on an explicit workspace (sized for this operator); used by
+// h2_gemv_ex with the handle's workspace and by the server with a slot's.
+int gemv_ws(h2_op_s* h, const Workspace& w, bool trans, double alpha, const double* X, int64_t ldx, int64_t nv,
+            double beta, double* Y, int64_t ldy, int prec, hipStream_t s) {
+  int rc;
+  if (prec == H2_PREC_FP32 && (rc = prepare_f32(h)) != H2_OK) return rc;
+  if (prec == H2_PREC_BF16) {
+    if (trans || !h->mfma_ok || w.cap < kPassVectorsMfma) {
+      set_error("BF16 needs op 'N' and the MFMA path");
+      return H2_EUNSUPPORTED;
+    }
+    if ((rc = prepare_bf16(h)) != H2_OK) return rc;
+  }
+  // multi-vector products of op 'N' (and every BF16 product) go to the MFMA kernels
+  const bool mfma = !trans && h->mfma_ok && w.cap >= kPassVectorsMfma && (nv > kPassVectors || prec == H2_PREC_BF16);
+  const int64_t pass = mfma ? kPassVectorsMfma : kPassVectors;
+  for (int64_t v0 = 0; v0 < nv; v0 += pass) {
+    const int nvc = (int)std::min<int64_t>(pass, nv - v0);
+    rc = gemv_pass(h, w, trans, alpha, X + ldx * v0, ldx, nvc, beta, Y + ldy * v0, ldy, s,
+                   mfma ? (nvc + 15) / 16 * 16 : 0, prec);
+    if (rc != H2_OK) return rc;
+  }
+  return H2_OK;
+}
+
+int check_gemv_args(h2_op_s* h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double* Y,
+                    int64_t ldy, int prec, bool* trans) {
   if (!h) { set_error("null handle"); return H2_EINVAL; }
-  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32) { set_error("unknown precision"); return H2_EINVAL; }
-  const bool trans = op == 'T' || op == 't';
-  if (!trans && op != 'N' && op != 'n') { set_error("op must be 'N' or 'T'"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_BF16) {
+    set_error("unknown precision");
+    return H2_EINVAL;
+  }
+  *trans = op == 'T' || op == 't';
+  if (!*trans && op != 'N' && op != 'n') { set_error("op must be 'N' or 'T'"); return H2_EINVAL; }
   if (nv < 0) { set_error("nv < 0"); return H2_EINVAL; }
   if (nv == 0) return H2_OK;
   if (!Y || ldy < h->n) { set_error("bad Y or ldy"); return H2_EINVAL; }
@@ -544,6 +617,16 @@ int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx,
     const char* ye = reinterpret_cast<const char*>(Y + ldy * (nv - 1) + h->n);
     if (xb < ye && yb < xe) { set_error("X and Y overlap"); return H2_EINVAL; }
   }
+  return H2_OK;
+}
+}  // namespace h2
+
+extern "C" {
+int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double beta,
+               double* Y, int64_t ldy, int prec, void* stream) {
+  bool trans = false;
+  int rc = check_gemv_args(h, op, alpha, X, ldx, nv, Y, ldy, prec, &trans);
+  if (rc != H2_OK || nv == 0) return rc;
   DeviceGuard guard(h->device);
   if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -551,19 +634,8 @@ int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx,
     HIP_TRY(launch_scale(Y, ldy, h->n, nv, beta, s), "scale");
     return H2_OK;
   }
-  int rc = ensure_workspace(h, nv);
-  if (rc != H2_OK) return rc;
-  const bool f32 = prec == H2_PREC_FP32;
-  if (f32 && (rc = prepare_f32(h)) != H2_OK) return rc;
-  // multi-vector products of op 'N' go to the MFMA kernels
-  const bool mfma = !trans && nv > kPassVectors && h->mfma_ok && h->cap >= kPassVectorsMfma;
-  const int64_t pass = mfma ? kPassVectorsMfma : kPassVectors;
-  for (int64_t v0 = 0; v0 < nv; v0 += pass) {
-    const int nvc = (int)std::min<int64_t>(pass, nv - v0);
-    rc = gemv_pass(h, trans, alpha, X + ldx * v0, ldx, nvc, beta, Y + ldy * v0, ldy, s,
-                   mfma ? (nvc + 15) / 16 * 16 : 0, f32);
-    if (rc != H2_OK) return rc;
-  }
+  if ((rc = ensure_workspace(h, prec == H2_PREC_BF16 ? kPassVectorsMfma : nv)) != H2_OK) return rc;
+  if ((rc = gemv_ws(h, h->ws, trans, alpha, X, ldx, nv, beta, Y, ldy, prec, s)) != H2_OK) return rc;
   if (h->profiling) ++h->prof.calls;
   return H2_OK;
 }
@@ -576,10 +648,10 @@ int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, in
 int h2_prepare(h2_handle h, int prec) {
   if (!h) { set_error("null handle"); return H2_EINVAL; }
   if (prec == H2_PREC_FP64) return H2_OK;
-  if (prec != H2_PREC_FP32) { set_error("unknown precision"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP32 && prec != H2_PREC_BF16) { set_error("unknown precision"); return H2_EINVAL; }
   DeviceGuard guard(h->device);
   if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
-  return prepare_f32(h);
+  return prec == H2_PREC_FP32 ? prepare_f32(h) : prepare_bf16(h);
 }
 
 int h2_stats(h2_handle h, h2_stats_t* st) {

@@ -12,6 +12,8 @@
 
 #include "h2.h"
 
+struct h2_op_s;
+
 namespace h2 {
 
 // Largest rank and leaf size the kernels accept (one output entry per
@@ -180,6 +182,27 @@ void emit_rows_N(const OpLayout& L, const RowBases& B, RowsN* R);
 void append_row(RowTables& t, const RowSpec& r);
 int64_t row_work(const RowSpec& r);
 
+// Per-product scratch: X~ and the dense partial (n x cap), x^ and y^
+// (H x cap) in doubles; the streaming path uses them column-major with up
+// to 4 columns, the MFMA path row-major with up to 64.  The side stream and
+// events fork and join the dense phase.  One workspace serves one product at
+// a time; concurrent products need one each.
+struct Workspace {
+  int64_t n = 0, H = 0, cap = 0;
+  double *xt = nullptr, *xh = nullptr, *yh = nullptr, *zn = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap);
+// The product of h2_gemv_ex on an explicit workspace (w.n >= n, w.H >= H),
+// after check_gemv_args; alpha != 0 and nv > 0.
+int gemv_ws(h2_op_s* h, const Workspace& w, bool trans, double alpha, const double* X, int64_t ldx, int64_t nv,
+            double beta, double* Y, int64_t ldy, int prec, hipStream_t s);
+int check_gemv_args(h2_op_s* h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double* Y,
+                    int64_t ldy, int prec, bool* trans);
+void ws_destroy(Workspace* w);
+int64_t ws_bytes(int64_t n, int64_t H, int64_t cap);
+
 }  // namespace h2
 
 struct h2_op_s {
@@ -196,6 +219,8 @@ struct h2_op_s {
   int64_t n_trans = 0;        // elements of d_trans
   float* d_mat32 = nullptr;   // FP32 copies of d_mat[0, n_lowrank) and of d_trans
   float* d_trans32 = nullptr;
+  void* d_mat16 = nullptr;    // BF16 copies of the op-'N' low-rank rows, row-major per row
+  void* d_trans16 = nullptr;
   int32_t* d_perm = nullptr;
   int32_t* d_pinv = nullptr;  // original index -> tree position
   bool mfma_ok = true;        // every op-'N' launch fits the MFMA row kernel
@@ -204,13 +229,7 @@ struct h2_op_s {
   h2::GatherTables gt;        // transposed rows of the 'T' plan
   h2::Plan planN, planT;
   int64_t index_bytes = 0;
-  hipStream_t side = nullptr;              // dense phase runs here, concurrently
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // workspace: X~ and the dense partial (n x cap), x^ and y^ (H x cap), in
-  // doubles per row; the streaming path uses them column-major with 4
-  // columns, the MFMA path row-major with up to 64
-  int64_t cap = 0;
-  double *d_xt = nullptr, *d_xh = nullptr, *d_yh = nullptr, *d_zn = nullptr;
+  h2::Workspace ws;  // the handle's own workspace (h2_gemv), allocated on first use
   // profiling
   bool profiling = false;
   std::vector<std::array<hipEvent_t, 9>> ev_pool;
@@ -247,6 +266,12 @@ struct BatchItem {
 hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t nmax, const int32_t* pinv,
                                 double* ws, int nvp, bool out, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+// BF16 path (data: __bf16, rows stored row-major; see the kernel file)
+hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                                 const void* data, const double* in, double* out, int nvp, int mode,
+                                 int max_rows, hipStream_t s, int64_t grid = 0);
+hipError_t launch_rows_to_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const double* src,
+                               void* dst, hipStream_t s);
 hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pinv, double* xt, int64_t n, int nv,
                                 int nvp, hipStream_t s);
 hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double alpha, double beta, double* Y,

@@ -541,10 +541,160 @@ hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t n
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// BF16 low-rank path: v_mfma_f32_16x16x32_bf16 (A[i][k] at lane i + 16*(k/8),
+// element k%8 of the lane's 8-vector; B[k][j] at lane j + 16*(k/8); C as in
+// the 16x16x4 forms), FP32 accumulation.  The BF16 copy stores every row's
+// matrix row-major (same offsets as the FP64 array, transposed within the
+// row), so a lane's eight consecutive k are one 16-byte load.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+template <int NT, int MAXT>
+__global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict__ rows, int64_t nrows,
+                                                       const int32_t* __restrict__ colend,
+                                                       const int64_t* __restrict__ in_off,
+                                                       const __bf16* __restrict__ data, const double* in,
+                                                       double* out, int mode) {
+  constexpr int NVP = 16 * NT;
+  constexpr int KC = 64;  // columns per LDS chunk (two k-steps of 32)
+  __shared__ __bf16 bs[NVP * KC];  // [vector][column]
+  __shared__ int32_t s_end[kNbMax];
+  __shared__ int64_t s_in[kNbMax];
+  __shared__ int64_t s_src[KC];
+  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+    __syncthreads();
+    const RowDesc R = rows[ri];
+    const int m = R.nrows;
+    if (m <= 0) continue;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = R.blk_end - R.blk_begin;
+    for (int i = tid; i < nb; i += kT) {
+      s_end[i] = colend[R.blk_begin + i];
+      s_in[i] = in_off[R.blk_begin + i];
+    }
+    __syncthreads();
+    const int ncols = nb > 0 ? s_end[nb - 1] : 0;
+    const int mt = (m + 15) >> 4;
+    const bool vec = (ncols % 8 == 0) && (R.data_off % 8 == 0);
+    f4 acc[MAXT][NT];
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    const int arow = lane & 15, kg = lane >> 4;
+    const __bf16* M = data + R.data_off;
+    for (int c0 = 0; c0 < ncols; c0 += KC) {
+      const int cn = min(KC, ncols - c0);
+      if (c0 > 0) __syncthreads();
+      if (tid < cn) {
+        const int col = c0 + tid;
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_end[mid] > col) hi = mid; else lo = mid + 1;
+        }
+        s_src[tid] = s_in[lo] + (col - (lo > 0 ? s_end[lo - 1] : 0));
+      }
+      __syncthreads();
+      for (int e = tid; e < KC * NVP; e += kT) {
+        const int j = e / NVP, v = e - j * NVP;
+        bs[v * KC + j] = j < cn ? (__bf16)(float)in[s_src[j] * NVP + v] : (__bf16)0.0f;
+      }
+      __syncthreads();
+      const int nsteps = (cn + 31) >> 5;
+#pragma unroll
+      for (int ti = 0; ti < MAXT; ++ti) {
+        const int tile = wave + 4 * ti;
+        if (tile >= mt) break;
+        const int r = tile * 16 + arow;
+        const bool rok = r < m;
+        for (int s = 0; s < nsteps; ++s) {
+          const int col = 32 * s + 8 * kg;  // within the chunk
+          bf8 a;
+          if (rok && vec && col + 8 <= cn) {
+            a = __builtin_nontemporal_load(reinterpret_cast<const bf8*>(M + (int64_t)r * ncols + c0 + col));
+          } else {
+#pragma unroll
+            for (int e2 = 0; e2 < 8; ++e2)
+              a[e2] = (rok && col + e2 < cn) ? M[(int64_t)r * ncols + c0 + col + e2] : (__bf16)0.0f;
+          }
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const bf8 b = *reinterpret_cast<const bf8*>(bs + (16 * j + arow) * KC + col);
+            acc[ti][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[ti][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int tile = wave + 4 * ti;
+      if (tile >= mt) break;
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = tile * 16 + 4 * kg + r;
+          if (a < m) {
+            double* o = out + (R.out_off + a) * NVP + 16 * j + arow;
+            if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
+            else *o += (double)acc[ti][j][r];
+          }
+        }
+    }
+  }
+}
+
+// BF16 copy of the rows' matrices: FP64 column-major m x ncols at data_off
+// becomes BF16 row-major at the same offset (rounded through FP32).
+__global__ void k_rows_to_bf16(const RowDesc* __restrict__ rows, const int32_t* __restrict__ colend,
+                               const double* __restrict__ src, __bf16* __restrict__ dst) {
+  const RowDesc R = rows[blockIdx.x];
+  const int m = R.nrows;
+  const int ncols = R.blk_end > R.blk_begin ? colend[R.blk_end - 1] : 0;
+  const int64_t total = (int64_t)m * ncols;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t a = e / ncols, j = e - a * ncols;  // row-major destination index e
+    dst[R.data_off + e] = (__bf16)(float)src[R.data_off + a + (int64_t)m * j];
+  }
+}
+
 // Reduced-precision copy of FP64 data (round to nearest).
 __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = (float)src[e];
+}
+
+hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                                 const void* data, const double* in, double* out, int nvp, int mode,
+                                 int max_rows, hipStream_t s, int64_t grid) {
+  if (nrows == 0) return hipSuccess;
+  const dim3 g((unsigned)(grid > 0 && grid < nrows ? grid : nrows)), block(kT);
+  const __bf16* d = static_cast<const __bf16*>(data);
+#define H2_BF(NT)                                                                                                  \
+  do {                                                                                                             \
+    if (max_rows <= 64)                                                                                            \
+      hipLaunchKernelGGL((k_rows_mfma_bf16<NT, 1>), g, block, 0, s, rows, nrows, colend, in_off, d, in, out, mode); \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_rows_mfma_bf16<NT, 4>), g, block, 0, s, rows, nrows, colend, in_off, d, in, out, mode); \
+  } while (0)
+  switch (nvp) {
+    case 16: H2_BF(1); break;
+    case 32: H2_BF(2); break;
+    case 48: H2_BF(3); break;
+    case 64: H2_BF(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef H2_BF
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_to_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const double* src,
+                               void* dst, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_to_bf16, dim3((unsigned)nrows), dim3(256), 0, s, rows, colend, src,
+                     static_cast<__bf16*>(dst));
+  return hipGetLastError();
 }
 
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {

@@ -63,3 +63,29 @@ def test_fp32_small_config(nv):
         rel = np.linalg.norm(got - want) / np.linalg.norm(want)
         assert 0 < rel < 1e-5, rel  # really reduced precision, and close
     g.close()
+
+
+TOL16 = 5e-2  # BF16 data and staged vectors (unit roundoff 2^-9) along ~2(q+2) roundings, FP32 accumulation
+
+
+@pytest.mark.parametrize("cfg", ["c1", "laplace3d"])
+@pytest.mark.parametrize("nv", [1, 16, 64])
+def test_bf16(cfg, nv):
+    from paper_2109_05451_amd import H2Operator, H2Error
+    if cfg == "c1":
+        buf = np.array(h2gen.build_config("c1_2d_4096").array, copy=True)
+    else:  # rank 64 (4x4x4): the 16-byte BF16 fragment loads
+        buf = np.array(h2gen.build(h2gen.points(6000, 3, 3), leaf=64, p=4, eta=0.7, kernel="laplace").array,
+                       copy=True)
+    ref = oracle.Oracle(buf)
+    g = H2Operator(buf)
+    X = h2gen.vectors(g.n, nv, 11)
+    want = ref.gemv(X)
+    B = ref.gemv(X, absval=True)
+    got = run(g, X, "N", precision="bf16")
+    assert np.all(np.abs(got - want) <= TOL16 * B), np.max(np.abs(got - want) / B)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert 0 < rel < 2e-2, rel
+    with pytest.raises(H2Error):
+        run(g, X, "T", precision="bf16")
+    g.close()
