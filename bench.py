@@ -308,7 +308,7 @@ def main():
     runs = [(nv, "fp64")]
     if not args.no_variants:
         runs += [(v, "fp64") for v in cfg["nv"] if v != nv]
-        runs += [(v, "fp32") for v in cfg["nv"]]
+        runs += [(v, p) for v in cfg["nv"] for p in cfg.get("precisions", ("fp32",))]
     results, ref_out = {}, {}
     for v, prec in runs:
         Xh = h2gen.vectors(g.n, v, cfg["seed_vec"])

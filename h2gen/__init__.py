@@ -27,9 +27,9 @@ CONFIGS = {
     "c1_2d_4096": dict(n=4096, dim=2, leaf=64, p=4, eta=0.7, kernel="exp", param=0.1,
                        seed_pts=1001, seed_vec=2001, nv=(1,)),
     "c2_2d_1m": dict(n=1 << 20, dim=2, leaf=64, p=6, eta=0.7, kernel="exp", param=0.1,
-                     seed_pts=1002, seed_vec=2002, nv=(1, 16)),
+                     seed_pts=1002, seed_vec=2002, nv=(1, 16), precisions=("fp32",)),
     "c3_3d_512k": dict(n=1 << 19, dim=3, leaf=64, p=4, eta=0.7, kernel="laplace", param=0.0,
-                       seed_pts=1003, seed_vec=2003, nv=(64,)),
+                       seed_pts=1003, seed_vec=2003, nv=(64,), precisions=("bf16", "fp32")),
 }
 
 _lib = None
@@ -62,18 +62,32 @@ def vectors(n: int, nv: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((nv, n)).T
 
 
-class H2Buffer:
-    """Owns a serialized representation in host memory (from the C++ builder)."""
+class _Memory:
+    """The builder's allocation; freed when the last reference goes."""
 
-    def __init__(self, ptr: int, nbytes: int, lib):
+    def __init__(self, ptr: int, lib):
         self.ptr = ptr
-        self.nbytes = nbytes
-        self.array = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(ptr))
         self._fin = weakref.finalize(self, lib.h2gen_free, ctypes.c_void_p(ptr))
 
+
+class H2Buffer:
+    """A serialized representation in host memory (from the C++ builder).
+
+    ``array`` is a uint8 view that keeps the allocation alive by itself, so it
+    stays valid after the H2Buffer object is gone; the memory is released when
+    the buffer and every view of it are gone."""
+
+    def __init__(self, ptr: int, nbytes: int, lib):
+        mem = _Memory(ptr, lib)
+        carr = (ctypes.c_uint8 * nbytes).from_address(ptr)
+        carr._owner = mem  # the view -> ctypes array -> owner chain keeps the memory alive
+        self.ptr = ptr
+        self.nbytes = nbytes
+        self.array = np.ctypeslib.as_array(carr)
+
     def free(self):
+        """Drop this object's reference (memory goes once no view remains)."""
         self.array = None
-        self._fin()
 
 
 def build(pts: np.ndarray, leaf: int, p: int, eta: float, kernel: str = "exp",

@@ -211,9 +211,10 @@ __global__ __launch_bounds__(kT) void k_rows_wide(const RowDesc* __restrict__ ro
 // dense partial are row-major with NVP = 16*NT vectors per row (padding
 // vectors are zero).  The same row lists as the streaming kernel are used:
 // out (m x NVP) = M (m x ncols, column-major) * B (ncols x NVP, gathered).
-// v_mfma_f64_16x16x4f64 lane layout (wave64): A[i][k] at lane i + 16k,
-// B[k][j] at lane j + 16k, and the 4 accumulator doubles of lane l hold
-// C[4*(l/16) + r][l%16], r = 0..3.
+// 16x16x4 MFMA lane layouts (wave64, measured on gfx950): A[i][k] at lane
+// i + 16k, B[k][j] at lane j + 16k; accumulator element r (0..3) of lane l
+// holds C[4r + l/16][l%16] for v_mfma_f64_16x16x4f64 and
+// C[4(l/16) + r][l%16] for v_mfma_f32_16x16x4f32.
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // X~ (tree order, row-major NVP) from X (original order, column-major):
@@ -343,7 +344,8 @@ __global__ __launch_bounds__(kT) void k_rows_mfma(const RowDesc* __restrict__ ro
       }
     }
   }
-  // epilogue: lane holds C[4*(lane/16) + r][lane%16] of each of its tiles
+  // epilogue: accumulator element r of the lane is row 4r + lane/16 (FP64)
+  // or 4*(lane/16) + r (FP32) of each of its tiles, column lane%16
 #pragma unroll
   for (int ti = 0; ti < MAXT; ++ti) {
     const int tile = wave + 4 * ti;
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(kT) void k_rows_mfma(const RowDesc* __restrict__ ro
     for (int j = 0; j < NT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = tile * 16 + 4 * akk + r;
+        const int a = tile * 16 + (sizeof(T) == 8 ? 4 * r + akk : 4 * akk + r);
         if (a < m) {
           double* o = out + (R.out_off + a) * NVP + 16 * j + arow;
           if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
