@@ -30,6 +30,24 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, datasheet
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector and matrix, datasheet
 
 
+def measured_traffic(config: str, nv: int):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    summary (FETCH_SIZE x calibration + WRITE_SIZE), or None when there is no
+    summary for this workload or the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_rows_{config}_nv{nv}.md")
+    src = os.path.join(ROOT, "paper_2109_05451_amd", "csrc", "h2_kernels.hip")
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    text = open(path).read()
+    m5 = re.search(r"kernel_source_md5: `([0-9a-f]+)`", text)
+    tb = re.search(r"traffic_bytes_per_launch[^:]*: ([0-9.eE+]+)", text)
+    if not m5 or not tb or m5.group(1) != hashlib.md5(open(src, "rb").read()).hexdigest():
+        return None
+    return float(tb.group(1))
+
+
 def algorithmic(st: dict, nv: int, beta_nonzero: bool = False) -> dict:
     """Algorithmic flops and bytes of one product (each stored entry read once;
     vector trees written and read once; X read, Y written once)."""
@@ -348,7 +366,8 @@ def main():
         achieved = alg["phase_bytes"][dom] / (dom_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roofline.update({"traffic": None, "kernel": f"{kname} ({dom} rows)",
+    roofline.update({"traffic": measured_traffic(args.config, nv) if dom == "dense" else None,
+                     "kernel": f"{kname} ({dom} rows)",
                      "bytes_per_launch": alg["phase_bytes"][dom], "flops_per_launch": alg["phase_flops"][dom],
                      "ms_per_launch": round(dom_ms, 4)})
     path_gbs = alg["bytes"] / (r["t_ms"] * 1e-3) / 1e9
