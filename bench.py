@@ -30,10 +30,11 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, datasheet
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector and matrix, datasheet
 
 
-def measured_traffic(config: str, nv: int):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    summary (FETCH_SIZE x calibration + WRITE_SIZE), or None when there is no
-    summary for this workload or the kernel source changed since it was taken."""
+def measured_traffic(config: str, nv: int, phase: str):
+    """HBM bytes per launch of the dominant kernel (the launch of ``phase`` rows)
+    from the committed rocprofv3 summary (FETCH_SIZE x calibration + WRITE_SIZE),
+    or None when there is no summary for this workload and phase or the kernel
+    source changed since it was taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_rows_{config}_nv{nv}.md")
@@ -42,7 +43,7 @@ def measured_traffic(config: str, nv: int):
         return None
     text = open(path).read()
     m5 = re.search(r"kernel_source_md5: `([0-9a-f]+)`", text)
-    tb = re.search(r"traffic_bytes_per_launch[^:]*: ([0-9.eE+]+)", text)
+    tb = re.search(r"traffic_bytes_per_launch \(" + phase + r" rows\): ([0-9.eE+]+)", text)
     if not m5 or not tb or m5.group(1) != hashlib.md5(open(src, "rb").read()).hexdigest():
         return None
     return float(tb.group(1))
@@ -352,23 +353,27 @@ def main():
     r = results[(nv, "fp64")]
     alg = r["alg"]
     gflops = alg["flops"] / (r["t_ms"] * 1e-3) / 1e9
-    # dominant kernel: the single-launch phase (coupling or dense) with the most
-    # algorithmic bytes; its bound follows from its arithmetic intensity
-    dom = max(("coupling", "dense"), key=lambda k: alg["phase_bytes"][k])
-    dom_ms = r["prof"][dom]
-    ai = alg["phase_flops"][dom] / alg["phase_bytes"][dom]
+    # dominant kernel: the launch with the most algorithmic bytes -- the coupling
+    # rows (one launch) or one of the two dense halves (the profile's dense time
+    # is the sum of both halves); its bound follows from its arithmetic intensity
+    launches = {"coupling": 1, "dense": 2}
+    dom = max(launches, key=lambda k: alg["phase_bytes"][k] / launches[k])
+    dom_ms = r["prof"][dom] / launches[dom]
+    dom_bytes = alg["phase_bytes"][dom] / launches[dom]
+    dom_flops = alg["phase_flops"][dom] / launches[dom]
+    ai = dom_flops / dom_bytes
     kname = "k_rows_mfma<double>" if nv > 4 else "k_rows<double>"
     if ai >= FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
-        achieved = alg["phase_flops"][dom] / (dom_ms * 1e-3) / 1e12
+        achieved = dom_flops / (dom_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
     else:
-        achieved = alg["phase_bytes"][dom] / (dom_ms * 1e-3) / 1e9
+        achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roofline.update({"traffic": measured_traffic(args.config, nv) if dom == "dense" else None,
+    roofline.update({"traffic": measured_traffic(args.config, nv, dom),
                      "kernel": f"{kname} ({dom} rows)",
-                     "bytes_per_launch": alg["phase_bytes"][dom], "flops_per_launch": alg["phase_flops"][dom],
+                     "bytes_per_launch": dom_bytes, "flops_per_launch": dom_flops,
                      "ms_per_launch": round(dom_ms, 4)})
     path_gbs = alg["bytes"] / (r["t_ms"] * 1e-3) / 1e9
     workloads = {

@@ -87,7 +87,9 @@ typedef struct {
   double ms_upsweep;      /* leaf products V^T x and transfer upsweep */
   double ms_coupling;     /* coupling products, all levels */
   double ms_downsweep;    /* transfer downsweep */
-  double ms_dense;        /* dense near-field blocks */
+  double ms_dense;        /* dense near-field blocks: the sum of the durations of its two
+                             halves on the side stream (the first runs beside the upsweep,
+                             the second beside the downsweep and the leaf expansion) */
   double ms_leaf_out;     /* leaf expansion U y^ and the alpha/beta update */
   double ms_total;        /* first to last event of each call, summed */
 } h2_profile_t;

@@ -165,8 +165,17 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
     for (int64_t hh = 1; hh <= q; ++hh) add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
     add_stream_phase(h, R.couple, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple);
     for (int64_t l = 1; l <= q; ++l) add_stream_phase(h, R.down[l - 1], ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
-    add_stream_phase(h, R.dense, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, true, plan.dense);
-    for (Launch& L : plan.dense) L.lowrank = false;
+    {
+      // two halves with the same mix of long and short rows (longest first in each)
+      std::stable_sort(R.dense.begin(), R.dense.end(),
+                       [](const RowSpec& a, const RowSpec& b) { return row_work(a) > row_work(b); });
+      std::vector<RowSpec> h1, h2;
+      for (size_t i = 0; i < R.dense.size(); ++i) (i % 2 ? h2 : h1).push_back(R.dense[i]);
+      add_stream_phase(h, h1, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense);
+      add_stream_phase(h, h2, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense2);
+      for (Launch& L : plan.dense) L.lowrank = false;
+      for (Launch& L : plan.dense2) L.lowrank = false;
+    }
     std::vector<Launch> outl;
     add_stream_phase(h, R.out, ARR_MAT, BUF_YH, BUF_ZN, MODE_FINAL, false, outl);
     if (outl.size() != 1) {
@@ -221,8 +230,14 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
         by_col[P.d_col[b]].push_back({oD + P.ddat[b], P.lo[P.leaf0 + t], 0, msz(P.leaf0 + t)});
     for (int64_t s = 0; s < P.nleaves; ++s)
       rows.push_back({0, P.lo[P.leaf0 + s], n, n, msz(P.leaf0 + s), std::move(by_col[s])});
-    add_gather_phase(h, rows, BUF_XT, BUF_ZN, plan.dense);
+    {
+      std::vector<RowSpec> h1, h2;
+      for (size_t i = 0; i < rows.size(); ++i) (i % 2 ? h2 : h1).push_back(rows[i]);
+      add_gather_phase(h, h1, BUF_XT, BUF_ZN, plan.dense);
+      add_gather_phase(h, h2, BUF_XT, BUF_ZN, plan.dense2);
+    }
     for (Launch& L : plan.dense) L.lowrank = false;
+    for (Launch& L : plan.dense2) L.lowrank = false;
     rows.clear();
     for (int64_t t = P.leaf0; t < P.nnodes; ++t)
       rows.push_back({oV + P.lo[t] * kr[q], P.lo[t], n, H, msz(t), {BlockRef{0, hoff[t], (int32_t)kr[q], 0}}});
@@ -279,7 +294,7 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
     perm[i] = (int32_t)P.perm[i];
     pinv[P.perm[i]] = (int32_t)i;
   }
-  for (const auto* v : {&h->planN.up, &h->planN.couple, &h->planN.down, &h->planN.dense})
+  for (const auto* v : {&h->planN.up, &h->planN.couple, &h->planN.down, &h->planN.dense, &h->planN.dense2})
     for (const Launch& L : *v)
       if (L.kind != KIND_STREAM) h->mfma_ok = false;
   int64_t ib = 0;
@@ -441,10 +456,10 @@ int prepare_bf16(h2_op_s* h) {
 int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const double* X, int64_t ldx, int nv,
               double beta, double* Y, int64_t ldy, hipStream_t s, int nvp, int prec) {
   const Plan& plan = trans ? h->planT : h->planN;
-  std::array<hipEvent_t, 9>* ev = nullptr;
+  std::array<hipEvent_t, 11>* ev = nullptr;
   if (h->profiling && &w == &h->ws) {
     if (h->ev_used == h->ev_pool.size()) {
-      std::array<hipEvent_t, 9> set{};
+      std::array<hipEvent_t, 11> set{};
       for (auto& e : set) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
       h->ev_pool.push_back(set);
     }
@@ -466,12 +481,18 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");
   STEP(mark(5, w.side));
   for (const Launch& L : plan.dense) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
-  STEP(mark(6, w.side));
-  HIP_TRY(hipEventRecord(w.ev_join, w.side), "hipEventRecord(join)");
+  STEP(mark(9, w.side));
   for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(2, s));
   for (const Launch& L : plan.couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(3, s));
+  // second half of the dense rows, beside the downsweep and the leaf expansion
+  HIP_TRY(hipEventRecord(w.ev_mid, s), "hipEventRecord(mid)");
+  HIP_TRY(hipStreamWaitEvent(w.side, w.ev_mid, 0), "hipStreamWaitEvent(mid)");
+  STEP(mark(10, w.side));
+  for (const Launch& L : plan.dense2) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
+  STEP(mark(6, w.side));
+  HIP_TRY(hipEventRecord(w.ev_join, w.side), "hipEventRecord(join)");
   for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(4, s));
   HIP_TRY(hipStreamWaitEvent(s, w.ev_join, 0), "hipStreamWaitEvent(join)");
@@ -555,7 +576,8 @@ int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
       (e = hipMalloc(reinterpret_cast<void**>(&w->zn), sizeof(double) * nn * cap)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming)) != hipSuccess) {
+      (e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&w->ev_mid, hipEventDisableTiming)) != hipSuccess) {
     ws_destroy(w);
     return hip_fail(e, "workspace allocation");
   }
@@ -568,6 +590,7 @@ void ws_destroy(Workspace* w) {
     if (p) (void)hipFree(p);
   if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
   if (w->ev_join) (void)hipEventDestroy(w->ev_join);
+  if (w->ev_mid) (void)hipEventDestroy(w->ev_mid);
   if (w->side) (void)hipStreamDestroy(w->side);
   *w = Workspace();
 }
@@ -679,14 +702,14 @@ int h2_profile_read(h2_handle h, h2_profile_t* out) {
     auto& e = h->ev_pool[i];
     HIP_TRY(hipEventSynchronize(e[8]), "hipEventSynchronize");
     HIP_TRY(hipEventSynchronize(e[6]), "hipEventSynchronize");
-    float t[9];
-    const int from[7] = {0, 1, 2, 3, 5, 7, 0}, to[7] = {1, 2, 3, 4, 6, 8, 8};
-    for (int k = 0; k < 7; ++k) HIP_TRY(hipEventElapsedTime(&t[k], e[from[k]], e[to[k]]), "hipEventElapsedTime");
+    float t[8];
+    const int from[8] = {0, 1, 2, 3, 5, 7, 0, 10}, to[8] = {1, 2, 3, 4, 9, 8, 8, 6};
+    for (int k = 0; k < 8; ++k) HIP_TRY(hipEventElapsedTime(&t[k], e[from[k]], e[to[k]]), "hipEventElapsedTime");
     h->prof.ms_permute += t[0];
     h->prof.ms_upsweep += t[1];
     h->prof.ms_coupling += t[2];
     h->prof.ms_downsweep += t[3];
-    h->prof.ms_dense += t[4];
+    h->prof.ms_dense += t[4] + t[7];
     h->prof.ms_leaf_out += t[5];
     h->prof.ms_total += t[6];
   }

@@ -111,7 +111,8 @@ struct Plan {
   std::vector<Launch> up;      // leaf products, then transfer levels q..1
   std::vector<Launch> couple;  // all levels at once (plus wide rows, if any)
   std::vector<Launch> down;    // transfer levels 1..q
-  std::vector<Launch> dense;   // dense leaf blocks (side stream)
+  std::vector<Launch> dense;   // dense leaf blocks, first half (side stream, beside the upsweep)
+  std::vector<Launch> dense2;  // second half (side stream, beside the downsweep and leaf expansion)
   Launch out;                  // leaf expansion + dense partial + alpha/beta update
 };
 
@@ -191,7 +192,7 @@ struct Workspace {
   int64_t n = 0, H = 0, cap = 0;
   double *xt = nullptr, *xh = nullptr, *yh = nullptr, *zn = nullptr;
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
 };
 int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap);
 // The product of h2_gemv_ex on an explicit workspace (w.n >= n, w.H >= H),
@@ -232,7 +233,7 @@ struct h2_op_s {
   h2::Workspace ws;  // the handle's own workspace (h2_gemv), allocated on first use
   // profiling
   bool profiling = false;
-  std::vector<std::array<hipEvent_t, 9>> ev_pool;
+  std::vector<std::array<hipEvent_t, 11>> ev_pool;
   size_t ev_used = 0;
   h2_profile_t prof{};
 };
