@@ -37,6 +37,8 @@ def _load():
         lib.h2o_gemv_rows.restype = ci
         lib.h2o_threads.argtypes = []
         lib.h2o_threads.restype = ci
+        lib.h2o_set_threads.argtypes = [ci]
+        lib.h2o_set_threads.restype = None
         lib.h2o_dense.argtypes = [vp, ch, vp]
         lib.h2o_dense.restype = ci
         _lib = lib
@@ -115,6 +117,11 @@ class Oracle:
 def threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().h2o_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads for the oracle's later OpenMP loops."""
+    _load().h2o_set_threads(int(t))
 
 
 def open_rep(buf) -> Oracle:

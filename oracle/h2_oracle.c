@@ -336,6 +336,15 @@ int h2o_threads(void) {
 #endif
 }
 
+/* Sets the threads of later parallel loops (t >= 1; a serial build ignores it). */
+void h2o_set_threads(int t) {
+#ifdef _OPENMP
+  if (t >= 1) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* the product                                                              */
 /* ------------------------------------------------------------------------ */

@@ -39,7 +39,9 @@ def explicit_bases(r, which):
     return basis
 
 
-def dense_tree_order(buf):
+def dense_tree_order(buf, include_dense=True):
+    """The matrix in tree order (with include_dense=False: its low-rank part,
+    the sum of the coupling blocks' contributions, only)."""
     r = fmt.parse(buf)
     n, q = r["n"], r["q"]
     lp, lo, hi = r["level_ptr"], r["lo"], r["hi"]
@@ -59,7 +61,7 @@ def dense_tree_order(buf):
                 A[lo[t]:hi[t], lo[s]:hi[s]] += Uh[t] @ S @ Vh[s].T
     doff = 0
     leaf0 = int(lp[q])
-    for ti in range(int(lp[q + 1] - lp[q])):
+    for ti in range(int(lp[q + 1] - lp[q]) if include_dense else 0):
         t = leaf0 + ti
         for b in range(int(r["d_rowptr"][ti]), int(r["d_rowptr"][ti + 1])):
             s = leaf0 + int(r["d_col"][b])
@@ -76,3 +78,37 @@ def dense_original_order(buf):
     A = np.zeros_like(At)
     A[np.ix_(perm, perm)] = At
     return A
+
+
+def coupling_blocks(r):
+    """(level, row node, column node) of every coupling block."""
+    lp = r["level_ptr"]
+    out = []
+    for l in range(r["q"] + 1):
+        rp, cl = r["s_rowptr"][l], r["s_col"][l]
+        for ti in range(int(lp[l + 1] - lp[l])):
+            for b in range(int(rp[ti]), int(rp[ti + 1])):
+                out.append((l, int(lp[l]) + ti, int(lp[l]) + int(cl[b])))
+    return out
+
+
+def block_row(Alr, r, i, rows=True, cols=False):
+    """The part of the low-rank matrix Alr (tree order) that node i's basis
+    must represent: with rows, for every coupling block (a, s) whose row node
+    a is i or an ancestor of i, the rows of i and the columns of s; with cols,
+    transposed, for every block (s, a) whose column node a is i or an
+    ancestor, the rows of s and the columns of i."""
+    lo, hi, par = r["lo"], r["hi"], r["parent"]
+    anc = {i}
+    c = i
+    while par[c] >= 0:
+        c = int(par[c])
+        anc.add(c)
+    parts = []
+    for _, t, s in coupling_blocks(r):
+        if rows and t in anc:
+            parts.append(Alr[lo[i]:hi[i], lo[s]:hi[s]])
+        if cols and s in anc:
+            parts.append(Alr[lo[t]:hi[t], lo[i]:hi[i]].T)
+    m = int(hi[i] - lo[i])
+    return np.hstack(parts) if parts else np.zeros((m, 0))
