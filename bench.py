@@ -74,6 +74,7 @@ def time_gpu(g, X, Y, nv, steps, warmup, torch, precision="fp64"):
     g.reserve(nv)
     if precision != "fp64":
         g.prepare(precision)
+    g.tune(nv, precision, stream.cuda_stream)
     for _ in range(warmup):
         g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream, precision)
     torch.cuda.synchronize()
@@ -94,6 +95,20 @@ def time_gpu(g, X, Y, nv, steps, warmup, torch, precision="fp64"):
     return wall, per_call, prof
 
 
+def latency_gpu(g, X, Y, nv, calls, torch):
+    """Per-call latency (HIP events around each call) over ``calls`` calls."""
+    n = g.n
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    torch.cuda.synchronize()
+    for s, e in ev:
+        s.record(stream)
+        g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream, "fp64")
+        e.record(stream)
+    torch.cuda.synchronize()
+    return np.array([s.elapsed_time(e) for s, e in ev])
+
+
 def cpu_baseline(buf, X, budget_s=30.0):
     """The oracle as it stands, timed on the host on a bounded sample: whole
     products at nv = 1 while the budget lasts (at least one)."""
@@ -107,8 +122,27 @@ def cpu_baseline(buf, X, budget_s=30.0):
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start + times[-1] > budget_s or len(times) >= 3:
             break
+    thr = oracle.threads()
+    # one product on a single thread, when the budget allows it
+    t_one = None
+    if times[0] * thr <= budget_s:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        o.gemv(X[:, :1])
+        t_one = time.perf_counter() - t0
+        oracle.set_threads(thr)
     o.close()
-    return float(np.mean(times)), len(times), oracle.threads()
+    return float(np.mean(times)), len(times), thr, t_one
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def batch_ops(count=256, seed0=3000):
@@ -283,6 +317,8 @@ def main():
     ap.add_argument("--nv", type=int, default=None, help="vectors of the headline run (default: config's first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=100,
+                    help="individually timed calls of the headline run for p50/p99 (0: use the timed steps)")
     ap.add_argument("--batch-count", type=int, default=256, help="operators of the batched workload")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -341,6 +377,9 @@ def main():
         phases = {k[3:]: prof[k] / prof["calls"] for k in prof if k.startswith("ms_")}
         res = dict(wall=wall, per_call=per_call, t_ms=t_ms, prof=phases, alg=alg,
                    p50=float(np.percentile(per_call, 50)), p99=float(np.percentile(per_call, 99)))
+        if (v, prec) == (nv, "fp64") and args.latency_calls > 0:
+            lat = latency_gpu(g, X, Y, v, args.latency_calls, torch)
+            res.update(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)), lat_samples=lat.size)
         Yh = Y.cpu().numpy()
         if prec == "fp64":
             ref_out[v] = Yh
@@ -391,7 +430,8 @@ def main():
         "roofline": roofline,
         "path": {"gb_per_s": round(path_gbs, 1), "hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
                  "alg_bytes": alg["bytes"], "alg_flops": alg["flops"], "phases_ms": r["prof"]},
-        "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4), "samples": len(r["per_call"])},
+        "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4),
+                       "samples": int(r.get("lat_samples", len(r["per_call"])))},
         "variants": [{"nv": v, "precision": prec, "ms": round(res["t_ms"], 4),
                       "gflops": round(res["alg"]["flops"] / (res["t_ms"] * 1e-3) / 1e9, 2),
                       "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
@@ -402,12 +442,15 @@ def main():
     if not args.no_cpu:
         Xh = h2gen.vectors(g.n, 1, cfg["seed_vec"])
         g.close()
-        t_cpu, reps, thr = cpu_baseline(buf.array, Xh)
+        t_cpu, reps, thr, t_one = cpu_baseline(buf.array, Xh)
         alg1 = algorithmic(st, 1)
         out["cpu_baseline"] = {"value": round(alg1["flops"] / t_cpu / 1e9, 3), "unit": "Gflop/s", "cores": thr,
                                "kind": "oracle",
                                "sample": f"{reps} whole product(s) of the same operator at nv=1, "
-                                         f"{t_cpu:.2f} s each"}
+                                         f"{t_cpu:.2f} s each",
+                               "cpu": cpu_model(),
+                               "single_thread_value": (round(alg1["flops"] / t_one / 1e9, 3)
+                                                       if t_one else None)}
     else:
         g.close()
     print(json.dumps(out), flush=True)

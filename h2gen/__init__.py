@@ -27,7 +27,7 @@ CONFIGS = {
     "c1_2d_4096": dict(n=4096, dim=2, leaf=64, p=4, eta=0.7, kernel="exp", param=0.1,
                        seed_pts=1001, seed_vec=2001, nv=(1,)),
     "c2_2d_1m": dict(n=1 << 20, dim=2, leaf=64, p=6, eta=0.7, kernel="exp", param=0.1,
-                     seed_pts=1002, seed_vec=2002, nv=(1, 16), precisions=("fp32",)),
+                     seed_pts=1002, seed_vec=2002, nv=(1, 16, 64), precisions=("fp32",)),
     "c3_3d_512k": dict(n=1 << 19, dim=3, leaf=64, p=4, eta=0.7, kernel="laplace", param=0.0,
                        seed_pts=1003, seed_vec=2003, nv=(64,), precisions=("bf16", "fp32")),
 }

@@ -151,6 +151,21 @@ int h2_prepare(h2_handle h, int prec);
  * to pass. */
 int h2_reserve(h2_handle h, int64_t nv_max);
 
+/* Autotune the multi-vector (MFMA) path of op 'N' for `nv` vectors in
+ * precision `prec`: for every launch of the product, each candidate chunk
+ * width (32 or 64 columns; BF16 has 64 only) and grid (one workgroup per
+ * row, or a persistent grid of 1024, 2048 or 4096 workgroups) is timed with
+ * HIP events on `stream` (three runs, the first discarded) on zeroed
+ * workspace buffers, and the fastest is kept for later calls in that
+ * precision (the dense rows, always FP64, keep theirs in the FP64 entry).
+ * Results do not depend on the choice: every candidate sums each output in
+ * the same order, so they are bitwise identical.  No-op for nv <= 4 outside
+ * BF16 (the streaming kernel has nothing to tune).  Synchronous; must not run concurrently with other calls on the
+ * handle (it uses the handle's workspace).
+ * Errors: H2_EINVAL (null handle, nv < 0, unknown precision), H2_ENOMEM,
+ * H2_EHIP. */
+int h2_tune(h2_handle h, int64_t nv, int prec, void* stream);
+
 /* Fill *st with the operator's structure and stored-entry counts. */
 int h2_stats(h2_handle h, h2_stats_t* st);
 

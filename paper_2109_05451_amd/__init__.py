@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libh2gemv.so")
 H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 # exported symbols of include/h2.h, in declaration order
-EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve",
+EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve", "h2_tune",
            "h2_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.h2_prepare.restype = ci
     lib.h2_reserve.argtypes = [vp, i64]
     lib.h2_reserve.restype = ci
+    lib.h2_tune.argtypes = [vp, i64, ci, vp]
+    lib.h2_tune.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
     lib.h2_stats.restype = ci
     lib.h2_n.argtypes = [vp]
@@ -190,6 +192,10 @@ class H2Operator:
 
     def prepare(self, precision: str):
         _check(load_library().h2_prepare(self._h, PRECISIONS[precision]))
+
+    def tune(self, nv: int, precision: str = "fp64", stream: int = 0):
+        """Autotune the multi-vector path for nv vectors (synchronous)."""
+        _check(load_library().h2_tune(self._h, nv, PRECISIONS[precision], stream or None))
 
     def gemv_raw(self, op: str, alpha: float, x_ptr: int, ldx: int, nv: int, beta: float, y_ptr: int,
                  ldy: int, stream: int = 0, precision: str = "fp64"):

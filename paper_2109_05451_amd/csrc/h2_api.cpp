@@ -372,10 +372,15 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   double* bufs[4] = {w.xt, w.xh, w.yh, w.zn};
   const bool lowp = prec == H2_PREC_FP32 && L.lowrank && L.kind != KIND_WIDE;
   if (prec == H2_PREC_BF16 && L.lowrank && nvp > 0) {
+    // x^ lives as BF16 column-major [vector][ld16] in the x^ buffer's memory
+    // (H * cap doubles hold ld16 * nvp BF16 values)
+    const int64_t ld16 = (h->H + 7) / 8 * 8;
+    const bool in16 = L.in == BUF_XH, out16 = mode_override < 0 && L.out == BUF_XH;
     const hipError_t eb = launch_rows_mfma_bf16(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend,
                                                 h->rt.d_in_off, L.arr == ARR_TRANS ? h->d_trans16 : h->d_mat16,
-                                                bufs[L.in], bufs[mode_override >= 0 ? BUF_ZN : L.out], nvp,
-                                                mode_override >= 0 ? mode_override : L.mode, L.max_rows, s);
+                                                bufs[L.in], in16, ld16, bufs[mode_override >= 0 ? BUF_ZN : L.out],
+                                                out16, ld16, nvp, mode_override >= 0 ? mode_override : L.mode,
+                                                L.max_rows, s, L.gridp[H2_PREC_BF16]);
     if (eb != hipSuccess) return hip_fail(eb, "kernel launch");
     return H2_OK;
   }
@@ -385,10 +390,11 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   const int mode = mode_override >= 0 ? mode_override : L.mode;
   hipError_t e = hipSuccess;
   if (nvp > 0) {
+    const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     e = lowp ? launch_rows_mfma<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s)
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi])
              : launch_rows_mfma<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s);
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi]);
   } else if (L.kind == KIND_STREAM) {
     e = lowp ? launch_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off, data32,
                                   bufs[L.in], out, nv, mode, ep, s)
@@ -561,7 +567,8 @@ int h2_reserve(h2_handle h, int64_t nv_max) {
 
 namespace h2 {
 int64_t ws_bytes(int64_t n, int64_t H, int64_t cap) {
-  return (int64_t)sizeof(double) * (2 * std::max<int64_t>(n, 1) + 2 * std::max<int64_t>(H, 1)) * cap;
+  return (int64_t)sizeof(double) *
+         (2 * std::max<int64_t>(n, 1) + std::max<int64_t>(H, 8) + std::max<int64_t>(H, 1)) * cap;
 }
 
 int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
@@ -571,7 +578,9 @@ int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
   const int64_t nn = std::max<int64_t>(n, 1), Hs = std::max<int64_t>(H, 1);
   hipError_t e;
   if ((e = hipMalloc(reinterpret_cast<void**>(&w->xt), sizeof(double) * nn * cap)) != hipSuccess ||
-      (e = hipMalloc(reinterpret_cast<void**>(&w->xh), sizeof(double) * Hs * cap)) != hipSuccess ||
+      // at least 8 rows: the BF16 path keeps x^ as BF16 [nvp][round_up(H, 8)] in this memory
+      (e = hipMalloc(reinterpret_cast<void**>(&w->xh), sizeof(double) * std::max<int64_t>(Hs, 8) * cap)) !=
+          hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void**>(&w->yh), sizeof(double) * Hs * cap)) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void**>(&w->zn), sizeof(double) * nn * cap)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking)) != hipSuccess ||
@@ -675,6 +684,81 @@ int h2_prepare(h2_handle h, int prec) {
   DeviceGuard guard(h->device);
   if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
   return prec == H2_PREC_FP32 ? prepare_f32(h) : prepare_bf16(h);
+}
+
+int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
+  if (!h || nv < 0) { set_error("bad handle or nv"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_BF16) {
+    set_error("unknown precision");
+    return H2_EINVAL;
+  }
+  if (nv <= kPassVectors && prec != H2_PREC_BF16) return H2_OK;  // streaming path: nothing to tune
+  DeviceGuard guard(h->device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  int rc;
+  if ((rc = h2_prepare(h, prec)) != H2_OK) return rc;
+  if ((rc = ensure_workspace(h, prec == H2_PREC_BF16 ? kPassVectorsMfma : nv)) != H2_OK) return rc;
+  if (!h->mfma_ok) return H2_OK;
+  const int nvp = (int)std::min<int64_t>((nv + 15) / 16 * 16, kPassVectorsMfma);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Workspace& w = h->ws;
+  // the candidates run on zeroed buffers (their timing does not depend on the values)
+  HIP_TRY(hipMemsetAsync(w.xt, 0, sizeof(double) * std::max<int64_t>(w.n, 1) * w.cap, s), "hipMemsetAsync");
+  HIP_TRY(hipMemsetAsync(w.xh, 0, sizeof(double) * std::max<int64_t>(w.H, 8) * w.cap, s), "hipMemsetAsync");
+  HIP_TRY(hipMemsetAsync(w.yh, 0, sizeof(double) * std::max<int64_t>(w.H, 1) * w.cap, s), "hipMemsetAsync");
+  HIP_TRY(hipMemsetAsync(w.zn, 0, sizeof(double) * std::max<int64_t>(w.n, 1) * w.cap, s), "hipMemsetAsync");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return H2_EHIP;
+  }
+  const Epilogue ep{w.zn, h->d_perm, 1.0, 0.0, nullptr, 0, h->n};
+  auto tune_one = [&](Launch& L, int mode_override) -> int {
+    const int pi = L.lowrank ? prec : H2_PREC_FP64;
+    const int kcs[2] = {32, 64};
+    const int64_t grids[4] = {0, 1024, 2048, 4096};
+    float best = 1e30f;
+    int best_kc = L.kcp[pi];
+    int64_t best_grid = L.gridp[pi];
+    for (int kc : kcs) {
+      if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
+      for (int64_t g : grids) {
+        if (g != 0 && g >= L.row_count) continue;
+        Launch T = L;
+        T.kcp[pi] = kc;
+        T.gridp[pi] = g;
+        float tsum = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {
+          HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
+          int r = run_launch(h, w, T, nvp, ep, s, nvp, mode_override, L.lowrank ? prec : H2_PREC_FP64);
+          if (r != H2_OK) return r;
+          HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
+          HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+          float ms = 0.0f;
+          HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+          if (rep > 0) tsum += ms;  // the first repetition warms up
+        }
+        if (tsum < best) {
+          best = tsum;
+          best_kc = kc;
+          best_grid = g;
+        }
+      }
+    }
+    L.kcp[pi] = best_kc;
+    L.gridp[pi] = best_grid;
+    return H2_OK;
+  };
+  Plan& plan = h->planN;
+  for (auto* v : {&plan.up, &plan.couple, &plan.down, &plan.dense, &plan.dense2})
+    for (Launch& L : *v)
+      if ((rc = tune_one(L, -1)) != H2_OK) break;
+  if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int h2_stats(h2_handle h, h2_stats_t* st) {

@@ -104,6 +104,11 @@ struct Launch {
   bool lowrank = true;                    // false for the dense near-field phase (always FP64)
   int kc = 64;                            // MFMA path: columns per LDS chunk (tuned in batches)
   int64_t grid = 0;                       // MFMA path: workgroups (0 = one per row; fewer = persistent)
+  // single-operator MFMA path, per precision of the launch (H2_PREC_*; the
+  // dense rows always use the FP64 entry): chunk columns and workgroups, set
+  // by h2_tune
+  int kcp[3] = {64, 64, 64};
+  int64_t gridp[3] = {0, 0, 0};
 };
 
 // The launch sequence of one operation (op 'N' or 'T').
@@ -269,8 +274,8 @@ hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t n
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 // BF16 path (data: __bf16, rows stored row-major; see the kernel file)
 hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
-                                 const void* data, const double* in, double* out, int nvp, int mode,
-                                 int max_rows, hipStream_t s, int64_t grid = 0);
+                                 const void* data, const void* in, bool in16, int64_t ldb, void* out, bool out16,
+                                 int64_t ldo, int nvp, int mode, int max_rows, hipStream_t s, int64_t grid = 0);
 hipError_t launch_rows_to_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const double* src,
                                void* dst, hipStream_t s);
 hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pinv, double* xt, int64_t n, int nv,

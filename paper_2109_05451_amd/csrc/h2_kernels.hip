@@ -546,20 +546,26 @@ hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t n
 // ---------------------------------------------------------------------------
 // BF16 low-rank path: v_mfma_f32_16x16x32_bf16 (A[i][k] at lane i + 16*(k/8),
 // element k%8 of the lane's 8-vector; B[k][j] at lane j + 16*(k/8); C as in
-// the 16x16x4 forms), FP32 accumulation.  The BF16 copy stores every row's
-// matrix row-major (same offsets as the FP64 array, transposed within the
-// row), so a lane's eight consecutive k are one 16-byte load.
+// the FP32 16x16x4 form), FP32 accumulation.  The BF16 copy stores every
+// row's matrix row-major (same offsets as the FP64 array, transposed within
+// the row), so a lane's eight consecutive k are one 16-byte load.  The input
+// is either an FP64 row-major [row][NVP] buffer (the permuted X, the
+// downsweep tree y^) or the BF16 column-major [vector][ldb] tree x^ that the
+// upsweep launches of this path write (OUT16): x^ is rounded to BF16 once,
+// where it is produced, which is the rounding it gets when staged anyway.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+enum { BSRC_F64_RM = 0, BSRC_BF16_CM = 1 };
 
-template <int NT, int MAXT>
+template <int NT, int MAXT, int BSRC, bool OUT16>
 __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict__ rows, int64_t nrows,
                                                        const int32_t* __restrict__ colend,
                                                        const int64_t* __restrict__ in_off,
-                                                       const __bf16* __restrict__ data, const double* in,
-                                                       double* out, int mode) {
+                                                       const __bf16* __restrict__ data, const void* in,
+                                                       int64_t ldb, void* out, int64_t ldo, int mode) {
   constexpr int NVP = 16 * NT;
-  constexpr int KC = 64;  // columns per LDS chunk (two k-steps of 32)
-  __shared__ __bf16 bs[NVP * KC];  // [vector][column]
+  constexpr int KC = 64;       // columns per LDS chunk (two k-steps of 32)
+  constexpr int KCP = KC + 8;  // padded LDS row: 144 bytes, so 16 rows hit 16 distinct 16-byte bank groups
+  __shared__ __align__(16) __bf16 bs[NVP * KCP];  // [vector][column]
   __shared__ int32_t s_end[kNbMax];
   __shared__ int64_t s_in[kNbMax];
   __shared__ int64_t s_src[KC];
@@ -587,7 +593,27 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict
     const __bf16* M = data + R.data_off;
     for (int c0 = 0; c0 < ncols; c0 += KC) {
       const int cn = min(KC, ncols - c0);
-      if (c0 > 0) __syncthreads();
+      // this chunk's A fragments first, so that their loads are in flight
+      // while the input is staged
+      bf8 a[MAXT][2];
+#pragma unroll
+      for (int ti = 0; ti < MAXT; ++ti) {
+        const int tile = wave + 4 * ti;
+        const int r = tile * 16 + arow;
+        const bool rok = tile < mt && r < m;
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          const int col = 32 * st + 8 * kg;
+          if (rok && vec && col + 8 <= cn) {
+            a[ti][st] = __builtin_nontemporal_load(reinterpret_cast<const bf8*>(M + (int64_t)r * ncols + c0 + col));
+          } else {
+#pragma unroll
+            for (int e2 = 0; e2 < 8; ++e2)
+              a[ti][st][e2] = (rok && col + e2 < cn) ? M[(int64_t)r * ncols + c0 + col + e2] : (__bf16)0.0f;
+          }
+        }
+      }
+      if (c0 > 0) __syncthreads();  // previous chunk's LDS reads done
       if (tid < cn) {
         const int col = c0 + tid;
         int lo = 0, hi = nb - 1;
@@ -598,9 +624,33 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict
         s_src[tid] = s_in[lo] + (col - (lo > 0 ? s_end[lo - 1] : 0));
       }
       __syncthreads();
-      for (int e = tid; e < KC * NVP; e += kT) {
-        const int j = e / NVP, v = e - j * NVP;
-        bs[v * KC + j] = j < cn ? (__bf16)(float)in[s_src[j] * NVP + v] : (__bf16)0.0f;
+      if (BSRC == BSRC_BF16_CM) {
+        // 8 lanes cover one vector's 64 chunk columns (128 contiguous bytes
+        // when the columns are one aligned run of source rows)
+        const __bf16* src = static_cast<const __bf16*>(in);
+        for (int t = tid; t < NVP * (KC / 8); t += kT) {
+          const int g = t & 7, v = t >> 3, j0 = 8 * g;
+          const __bf16* sv = src + (int64_t)v * ldb;
+          bf8 val;
+          if (j0 + 8 <= cn && s_src[j0 + 7] == s_src[j0] + 7 && (s_src[j0] & 7) == 0) {
+            val = *reinterpret_cast<const bf8*>(sv + s_src[j0]);
+          } else {
+#pragma unroll
+            for (int e2 = 0; e2 < 8; ++e2) val[e2] = j0 + e2 < cn ? sv[s_src[j0 + e2]] : (__bf16)0.0f;
+          }
+          *reinterpret_cast<bf8*>(bs + v * KCP + j0) = val;
+        }
+      } else {
+        // consecutive lanes read consecutive vectors of one source row
+        const double* src = static_cast<const double*>(in);
+        for (int t = tid; t < NVP * (KC / 8); t += kT) {
+          const int v = t % NVP, j0 = 8 * (t / NVP);
+          bf8 val;
+#pragma unroll
+          for (int e2 = 0; e2 < 8; ++e2)
+            val[e2] = j0 + e2 < cn ? (__bf16)(float)src[s_src[j0 + e2] * NVP + v] : (__bf16)0.0f;
+          *reinterpret_cast<bf8*>(bs + v * KCP + j0) = val;
+        }
       }
       __syncthreads();
       const int nsteps = (cn + 31) >> 5;
@@ -608,22 +658,14 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict
       for (int ti = 0; ti < MAXT; ++ti) {
         const int tile = wave + 4 * ti;
         if (tile >= mt) break;
-        const int r = tile * 16 + arow;
-        const bool rok = r < m;
-        for (int s = 0; s < nsteps; ++s) {
-          const int col = 32 * s + 8 * kg;  // within the chunk
-          bf8 a;
-          if (rok && vec && col + 8 <= cn) {
-            a = __builtin_nontemporal_load(reinterpret_cast<const bf8*>(M + (int64_t)r * ncols + c0 + col));
-          } else {
 #pragma unroll
-            for (int e2 = 0; e2 < 8; ++e2)
-              a[e2] = (rok && col + e2 < cn) ? M[(int64_t)r * ncols + c0 + col + e2] : (__bf16)0.0f;
-          }
+        for (int st = 0; st < 2; ++st) {
+          if (st >= nsteps) break;
+          const int col = 32 * st + 8 * kg;
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
-            const bf8 b = *reinterpret_cast<const bf8*>(bs + (16 * j + arow) * KC + col);
-            acc[ti][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[ti][j], 0, 0, 0);
+            const bf8 b = *reinterpret_cast<const bf8*>(bs + (16 * j + arow) * KCP + col);
+            acc[ti][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ti][st], b, acc[ti][j], 0, 0, 0);
           }
         }
       }
@@ -638,9 +680,13 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict
         for (int r = 0; r < 4; ++r) {
           const int a = tile * 16 + 4 * kg + r;
           if (a < m) {
-            double* o = out + (R.out_off + a) * NVP + 16 * j + arow;
-            if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
-            else *o += (double)acc[ti][j][r];
+            if (OUT16) {
+              static_cast<__bf16*>(out)[(int64_t)(16 * j + arow) * ldo + R.out_off + a] = (__bf16)acc[ti][j][r];
+            } else {
+              double* o = static_cast<double*>(out) + (R.out_off + a) * NVP + 16 * j + arow;
+              if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
+              else *o += (double)acc[ti][j][r];
+            }
           }
         }
     }
@@ -668,17 +714,30 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 }
 
 hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
-                                 const void* data, const double* in, double* out, int nvp, int mode,
-                                 int max_rows, hipStream_t s, int64_t grid) {
+                                 const void* data, const void* in, bool in16, int64_t ldb, void* out, bool out16,
+                                 int64_t ldo, int nvp, int mode, int max_rows, hipStream_t s, int64_t grid) {
   if (nrows == 0) return hipSuccess;
+  if (out16 && mode != MODE_STORE) return hipErrorInvalidValue;
+  if ((in16 || out16) && (ldb % 8 != 0 || ldo % 8 != 0)) return hipErrorInvalidValue;
   const dim3 g((unsigned)(grid > 0 && grid < nrows ? grid : nrows)), block(kT);
   const __bf16* d = static_cast<const __bf16*>(data);
-#define H2_BF(NT)                                                                                                  \
-  do {                                                                                                             \
-    if (max_rows <= 64)                                                                                            \
-      hipLaunchKernelGGL((k_rows_mfma_bf16<NT, 1>), g, block, 0, s, rows, nrows, colend, in_off, d, in, out, mode); \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_rows_mfma_bf16<NT, 4>), g, block, 0, s, rows, nrows, colend, in_off, d, in, out, mode); \
+#define H2_BF4(NT, MAXT, BS, O16) \
+  hipLaunchKernelGGL((k_rows_mfma_bf16<NT, MAXT, BS, O16>), g, block, 0, s, rows, nrows, colend, in_off, d, in, \
+                     ldb, out, ldo, mode)
+#define H2_BF2(NT, MAXT)                                              \
+  do {                                                                \
+    if (in16) {                                                       \
+      if (out16) H2_BF4(NT, MAXT, BSRC_BF16_CM, true);                \
+      else H2_BF4(NT, MAXT, BSRC_BF16_CM, false);                     \
+    } else {                                                          \
+      if (out16) H2_BF4(NT, MAXT, BSRC_F64_RM, true);                 \
+      else H2_BF4(NT, MAXT, BSRC_F64_RM, false);                      \
+    }                                                                 \
+  } while (0)
+#define H2_BF(NT)                         \
+  do {                                    \
+    if (max_rows <= 64) H2_BF2(NT, 1);    \
+    else H2_BF2(NT, 4);                   \
   } while (0)
   switch (nvp) {
     case 16: H2_BF(1); break;
@@ -688,6 +747,8 @@ hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32
     default: return hipErrorInvalidValue;
   }
 #undef H2_BF
+#undef H2_BF2
+#undef H2_BF4
   return hipGetLastError();
 }
 

@@ -89,3 +89,28 @@ def test_bf16(cfg, nv):
     with pytest.raises(H2Error):
         run(g, X, "T", precision="bf16")
     g.close()
+
+
+@pytest.mark.parametrize("cfg", ["c1", "laplace3d"])
+def test_tune_keeps_results_bitwise(cfg):
+    """h2_tune only picks chunk widths and grids; every candidate sums each
+    output in the same order, so tuned results equal untuned ones bitwise."""
+    from paper_2109_05451_amd import H2Operator
+    if cfg == "c1":
+        buf = np.array(h2gen.build_config("c1_2d_4096").array, copy=True)
+    else:
+        buf = np.array(h2gen.build(h2gen.points(6000, 3, 5), leaf=64, p=4, eta=0.7, kernel="laplace").array,
+                       copy=True)
+    ref = oracle.Oracle(buf)
+    g = H2Operator(buf)
+    X = h2gen.vectors(g.n, 40, 12)
+    want = ref.gemv(X)
+    B = ref.gemv(X, absval=True)
+    for prec in ("fp64", "fp32", "bf16"):
+        before = run(g, X, "N", precision=prec)
+        g.tune(40, prec)
+        after = run(g, X, "N", precision=prec)
+        assert np.array_equal(before, after), prec
+        if prec == "fp64":
+            assert np.all(np.abs(after - want) <= 1e-12 * B)
+    g.close()
