@@ -166,6 +166,50 @@ int h2_reserve(h2_handle h, int64_t nv_max);
  * H2_EHIP. */
 int h2_tune(h2_handle h, int64_t nv, int prec, void* stream);
 
+/* Timings and sizes of one recompression (h2_compress). */
+typedef struct {
+  double ms_orthogonalize;  /* QR upsweeps and the transform of the coupling blocks */
+  double ms_reweight;       /* Gram matrices of the block rows and their downsweep */
+  double ms_truncate;       /* eigenproblems, new bases and transfers, bottom-up */
+  double ms_project;        /* projection of the coupling blocks on the new bases */
+  double ms_assemble;       /* building the new handle (downloads, schedules, uploads) */
+  int64_t lowrank_entries_before;  /* stored entries of U, E, V, F, S */
+  int64_t lowrank_entries_after;
+  double sigma_ref_row;     /* reference singular value of the row (and column) tree */
+  double sigma_ref_col;
+} h2_compress_info_t;
+
+/* Algebraic recompression (Section 5 of the paper): a new handle on the same
+ * device holding an H^2 representation of h's matrix with nested orthogonal
+ * bases of lower rank.  Steps, on the device: orthogonalize each basis tree
+ * (QR upsweep), weight every node by the block row its basis represents (own
+ * and ancestors' coupling blocks; block columns too for a shared basis),
+ * truncate bottom-up keeping the singular values above tau * sigma_ref
+ * (sigma_ref: the largest leaf value of the tree, the 2-norm of the largest
+ * low-rank block row), and project the coupling blocks on the new bases.
+ * Each level keeps one rank, the largest count its nodes keep.  Dense blocks
+ * are copied unchanged; stored points are not carried over.
+ *   tau     in [0, 1); values below about 1e-7 reach the rounding of the
+ *           squared singular values and keep more vectors than needed
+ *   out     receives the new handle (free it with h2_free)
+ *   info    optional timings and sizes (may be NULL)
+ *   stream  hipStream_t for the device work (NULL = null stream)
+ * Synchronous.  h is not modified.  Supported: ranks <= 64, leaf size times
+ * rank <= 8192, children times rank times parent rank <= 8192.
+ * Errors: H2_EINVAL (null arguments, tau outside [0, 1)), H2_EUNSUPPORTED
+ * (limits), H2_ENOMEM, H2_EHIP. */
+int h2_compress(h2_handle h, double tau, h2_handle* out, h2_compress_info_t* info, void* stream);
+
+/* Serialize a handle's representation into host memory `buf` of `cap`
+ * bytes (the format h2_load_mem reads; points are not included).  *needed
+ * receives the size; with buf == NULL only the size is returned.
+ * Errors: H2_EINVAL (null handle or size pointer, cap too small), H2_EHIP. */
+int h2_export(h2_handle h, void* buf, size_t cap, size_t* needed);
+
+/* Ranks per level of the row and column bases (arrays of at least depth + 1
+ * entries, `cap` their length).  Errors: H2_EINVAL. */
+int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
+
 /* Fill *st with the operator's structure and stored-entry counts. */
 int h2_stats(h2_handle h, h2_stats_t* st);
 

@@ -361,26 +361,28 @@ def truncate_tree(rep, leaves, tr, k, W, tau):
                 ntr[c] = Wn[i * kl:(i + 1) * kl, :]
                 Tp += ntr[c].T @ T[c] @ tr[c]
             T[p] = Tp
-    return nleaf, ntr, knew, T, sref, count
+    return nleaf, ntr, knew, T, sref, count, sig
 
 
 def compress(buf, tau: float):
     """Recompress a serialized representation to threshold tau (Sec. 5).
     Returns (serialized result, info) where info holds the new ranks, the
-    reference singular values and the per-node kept counts."""
+    reference singular values, and per node the kept count and the singular
+    values its truncation saw."""
     rep = orthogonalize(read(buf))
     Wr = weights(rep, "row")
     out = dict(rep)
-    out["U"], out["E"], kr, Tr, sr, cr = truncate_tree(rep, rep["U"], rep["E"], rep["krow"], Wr, tau)
+    out["U"], out["E"], kr, Tr, sr, cr, gr = truncate_tree(rep, rep["U"], rep["E"], rep["krow"], Wr, tau)
     if rep["shared"]:
-        kc, Tc, sc, cc = kr, Tr, sr, cr
+        kc, Tc, sc, cc, gc = kr, Tr, sr, cr, gr
     else:
         Wc = weights(rep, "col")
-        out["V"], out["F"], kc, Tc, sc, cc = truncate_tree(rep, rep["V"], rep["F"], rep["kcol"], Wc, tau)
+        out["V"], out["F"], kc, Tc, sc, cc, gc = truncate_tree(rep, rep["V"], rep["F"], rep["kcol"], Wc, tau)
     out["krow"], out["kcol"] = kr, kc
     out["S"] = [[Tr[t] @ blk @ Tc[s].T for (t, s), blk in zip(_blocks(rep, l), rep["S"][l])]
                 for l in range(rep["q"] + 1)]
-    info = dict(krow=kr, kcol=kc, sigma_ref_row=sr, sigma_ref_col=sc, count_row=cr, count_col=cc)
+    info = dict(krow=kr, kcol=kc, sigma_ref_row=sr, sigma_ref_col=sc, count_row=cr, count_col=cc,
+                sigma_row=gr, sigma_col=gc)
     return write(out), info
 
 

@@ -20,6 +20,7 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve", "h2_tune",
+           "h2_compress", "h2_export", "h2_ranks",
            "h2_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
@@ -35,6 +36,17 @@ class H2Stats(ctypes.Structure):
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class H2CompressInfo(ctypes.Structure):
+    _fields_ = [("ms_orthogonalize", ctypes.c_double), ("ms_reweight", ctypes.c_double),
+                ("ms_truncate", ctypes.c_double), ("ms_project", ctypes.c_double),
+                ("ms_assemble", ctypes.c_double), ("lowrank_entries_before", ctypes.c_int64),
+                ("lowrank_entries_after", ctypes.c_int64), ("sigma_ref_row", ctypes.c_double),
+                ("sigma_ref_col", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class H2Profile(ctypes.Structure):
@@ -92,6 +104,12 @@ def load_library(path: str = LIB_PATH):
     lib.h2_reserve.restype = ci
     lib.h2_tune.argtypes = [vp, i64, ci, vp]
     lib.h2_tune.restype = ci
+    lib.h2_compress.argtypes = [vp, dbl, ctypes.POINTER(vp), ctypes.POINTER(H2CompressInfo), vp]
+    lib.h2_compress.restype = ci
+    lib.h2_export.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.h2_export.restype = ci
+    lib.h2_ranks.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
+    lib.h2_ranks.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
     lib.h2_stats.restype = ci
     lib.h2_n.argtypes = [vp]
@@ -154,7 +172,9 @@ class H2Operator:
     def __init__(self, src, device: int = 0):
         lib = load_library()
         h = ctypes.c_void_p()
-        if isinstance(src, (str, os.PathLike)):
+        if isinstance(src, ctypes.c_void_p):  # an existing handle (owned from now on)
+            h = src
+        elif isinstance(src, (str, os.PathLike)):
             _check(lib.h2_load(os.fsencode(src), device, ctypes.byref(h)))
         else:
             b = np.ascontiguousarray(np.asarray(src).view(np.uint8).ravel())
@@ -173,6 +193,31 @@ class H2Operator:
             self.close()
         except Exception:
             pass
+
+    def compress(self, tau: float, stream: int = 0):
+        """Algebraic recompression to threshold tau: (new operator, info)."""
+        h = ctypes.c_void_p()
+        info = H2CompressInfo()
+        _check(load_library().h2_compress(self._h, float(tau), ctypes.byref(h), ctypes.byref(info),
+                                          stream or None))
+        return H2Operator(h, self.device), info.as_dict()
+
+    def export(self) -> np.ndarray:
+        """The serialized representation (uint8 array, no points)."""
+        lib = load_library()
+        need = ctypes.c_size_t()
+        _check(lib.h2_export(self._h, None, 0, ctypes.byref(need)))
+        buf = np.zeros(need.value // 8 + 1, dtype=np.uint64).view(np.uint8)[:need.value]
+        _check(lib.h2_export(self._h, buf.ctypes.data, buf.size, ctypes.byref(need)))
+        return buf
+
+    def ranks(self):
+        """Row and column ranks per level."""
+        depth = self.stats()["depth"]
+        kr = (ctypes.c_int64 * (depth + 1))()
+        kc = (ctypes.c_int64 * (depth + 1))()
+        _check(load_library().h2_ranks(self._h, kr, kc, depth + 1))
+        return np.array(kr[:], dtype=np.int64), np.array(kc[:], dtype=np.int64)
 
     def stats(self) -> dict:
         st = H2Stats()
@@ -362,4 +407,4 @@ class H2Server:
             pass
 
 
-__all__ = ["H2Operator", "H2Batch", "H2Server", "H2Error", "load_library", "validate", "EXPORTS"]
+__all__ = ["H2CompressInfo", "H2Operator", "H2Batch", "H2Server", "H2Error", "load_library", "validate", "EXPORTS"]

@@ -117,7 +117,7 @@ void free_device(h2_op_s* h) {
 }
 
 // Build plans and upload; the handle's device is current.
-int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
+int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* d_dense) {
   const int64_t q = P.q, n = P.n;
   const int64_t* lp = P.level_ptr;
   h->n = n; h->q = q; h->nnodes = P.nnodes; h->nleaves = P.nleaves; h->leaf0 = P.leaf0;
@@ -164,6 +164,20 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
     add_stream_phase(h, R.up[0], ARR_TRANS, BUF_XT, BUF_XH, MODE_STORE, false, plan.up);
     for (int64_t hh = 1; hh <= q; ++hh) add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
     add_stream_phase(h, R.couple, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple);
+    {
+      auto by_pos = [](const RowSpec& a, const RowSpec& b) { return a.out_off < b.out_off; };
+      std::vector<RowSpec> loc = R.couple;
+      std::stable_sort(loc.begin(), loc.end(), by_pos);
+      add_stream_phase(h, loc, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, false, plan.couple_loc);
+      loc = R.dense;
+      std::stable_sort(loc.begin(), loc.end(), by_pos);
+      const size_t half = loc.size() / 2;
+      std::vector<RowSpec> h1(loc.begin(), loc.begin() + half), h2(loc.begin() + half, loc.end());
+      add_stream_phase(h, h1, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense_loc);
+      add_stream_phase(h, h2, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense2_loc);
+      for (auto* v : {&plan.dense_loc, &plan.dense2_loc})
+        for (Launch& L : *v) L.lowrank = false;
+    }
     for (int64_t l = 1; l <= q; ++l) add_stream_phase(h, R.down[l - 1], ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
     {
       // two halves with the same mix of long and short rows (longest first in each)
@@ -287,14 +301,24 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h) {
   const int64_t mat_bytes = P.off_end - P.off_U;
   if (mat_bytes > 0) {
     HIP_TRY(hipMalloc(reinterpret_cast<void**>(&h->d_mat), mat_bytes), "hipMalloc(matrix data)");
-    HIP_TRY(hipMemcpy(h->d_mat, buf + P.off_U, mat_bytes, hipMemcpyHostToDevice), "hipMemcpy(matrix data)");
+    const int64_t host_bytes = d_dense ? P.off_D - P.off_U : mat_bytes;
+    if (host_bytes > 0)
+      HIP_TRY(hipMemcpy(h->d_mat, buf + P.off_U, host_bytes, hipMemcpyHostToDevice), "hipMemcpy(matrix data)");
+    if (d_dense && P.off_end > P.off_D)
+      HIP_TRY(hipMemcpy(reinterpret_cast<uint8_t*>(h->d_mat) + (P.off_D - P.off_U), d_dense, P.off_end - P.off_D,
+                        hipMemcpyDeviceToDevice),
+              "hipMemcpy(dense blocks)");
   }
+  h->prefix.assign((size_t)(P.off_U + 7) / 8, 0);
+  std::memcpy(h->prefix.data(), buf, (size_t)P.off_U);
+  h->prefix_len = P.off_U;
   std::vector<int32_t> perm(n), pinv(n);
   for (int64_t i = 0; i < n; ++i) {
     perm[i] = (int32_t)P.perm[i];
     pinv[P.perm[i]] = (int32_t)i;
   }
-  for (const auto* v : {&h->planN.up, &h->planN.couple, &h->planN.down, &h->planN.dense, &h->planN.dense2})
+  for (const auto* v : {&h->planN.up, &h->planN.couple, &h->planN.down, &h->planN.dense, &h->planN.dense2,
+                        &h->planN.couple_loc, &h->planN.dense_loc, &h->planN.dense2_loc})
     for (const Launch& L : *v)
       if (L.kind != KIND_STREAM) h->mfma_ok = false;
   int64_t ib = 0;
@@ -336,7 +360,7 @@ struct DeviceGuard {
   }
 };
 
-int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out) {
+int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, const double* d_dense = nullptr) {
   if (!out) { set_error("null output handle"); return H2_EINVAL; }
   *out = nullptr;
   Parsed P;
@@ -351,7 +375,8 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out) {
   if (!h) { set_error("out of host memory"); return H2_ENOMEM; }
   h->device = device;
   try {
-    rc = build_handle(buf, P, h);
+    rc = build_handle(buf, P, h, d_dense);
+    h->file_len = len;
   } catch (const std::bad_alloc&) {
     set_error("out of host memory while building schedules");
     rc = H2_ENOMEM;
@@ -380,7 +405,7 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
                                                 h->rt.d_in_off, L.arr == ARR_TRANS ? h->d_trans16 : h->d_mat16,
                                                 bufs[L.in], in16, ld16, bufs[mode_override >= 0 ? BUF_ZN : L.out],
                                                 out16, ld16, nvp, mode_override >= 0 ? mode_override : L.mode,
-                                                L.max_rows, s, L.gridp[H2_PREC_BF16]);
+                                                L.max_rows, s, L.gridp[H2_PREC_BF16], L.remapp[H2_PREC_BF16]);
     if (eb != hipSuccess) return hip_fail(eb, "kernel launch");
     return H2_OK;
   }
@@ -392,9 +417,11 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     e = lowp ? launch_rows_mfma<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi])
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
+                                       L.remapp[pi])
              : launch_rows_mfma<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi]);
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
+                                        L.remapp[pi]);
   } else if (L.kind == KIND_STREAM) {
     e = lowp ? launch_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off, data32,
                                   bufs[L.in], out, nv, mode, ep, s)
@@ -462,6 +489,12 @@ int prepare_bf16(h2_op_s* h) {
 int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const double* X, int64_t ldx, int nv,
               double beta, double* Y, int64_t ldy, hipStream_t s, int nvp, int prec) {
   const Plan& plan = trans ? h->planT : h->planN;
+  // tree-ordered coupling / dense rows on the multi-vector path when tuned so
+  const int pidx = prec == H2_PREC_FP32 ? 1 : prec == H2_PREC_BF16 ? 2 : 0;
+  const bool lc = !trans && nvp > 0 && h->loc_couple[pidx], ld = !trans && nvp > 0 && h->loc_dense[pidx];
+  const std::vector<Launch>& couple = lc ? plan.couple_loc : plan.couple;
+  const std::vector<Launch>& dense1 = ld ? plan.dense_loc : plan.dense;
+  const std::vector<Launch>& dense2 = ld ? plan.dense2_loc : plan.dense2;
   std::array<hipEvent_t, 11>* ev = nullptr;
   if (h->profiling && &w == &h->ws) {
     if (h->ev_used == h->ev_pool.size()) {
@@ -486,17 +519,17 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   HIP_TRY(hipEventRecord(w.ev_fork, s), "hipEventRecord(fork)");
   HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");
   STEP(mark(5, w.side));
-  for (const Launch& L : plan.dense) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
+  for (const Launch& L : dense1) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
   STEP(mark(9, w.side));
   for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(2, s));
-  for (const Launch& L : plan.couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  for (const Launch& L : couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(3, s));
   // second half of the dense rows, beside the downsweep and the leaf expansion
   HIP_TRY(hipEventRecord(w.ev_mid, s), "hipEventRecord(mid)");
   HIP_TRY(hipStreamWaitEvent(w.side, w.ev_mid, 0), "hipStreamWaitEvent(mid)");
   STEP(mark(10, w.side));
-  for (const Launch& L : plan.dense2) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
+  for (const Launch& L : dense2) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
   STEP(mark(6, w.side));
   HIP_TRY(hipEventRecord(w.ev_join, w.side), "hipEventRecord(join)");
   for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
@@ -516,6 +549,10 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
 }
 
 }  // namespace
+
+int load_handle(const uint8_t* buf, int64_t len, int device, const double* d_dense, h2_handle* out) {
+  return load_common(buf, len, device, out, d_dense);
+}
 }  // namespace h2
 
 using namespace h2;
@@ -715,47 +752,73 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     return H2_EHIP;
   }
   const Epilogue ep{w.zn, h->d_perm, 1.0, 0.0, nullptr, 0, h->n};
-  auto tune_one = [&](Launch& L, int mode_override) -> int {
+  // best candidate of one launch; its time (ms, two timed runs) in *tbest
+  auto tune_one = [&](Launch& L, int mode_override, float* tbest) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
     const int kcs[2] = {32, 64};
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
-    int best_kc = L.kcp[pi];
+    int best_kc = L.kcp[pi], best_remap = L.remapp[pi];
     int64_t best_grid = L.gridp[pi];
     for (int kc : kcs) {
       if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
-      for (int64_t g : grids) {
-        if (g != 0 && g >= L.row_count) continue;
-        Launch T = L;
-        T.kcp[pi] = kc;
-        T.gridp[pi] = g;
-        float tsum = 0.0f;
-        for (int rep = 0; rep < 3; ++rep) {
-          HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
-          int r = run_launch(h, w, T, nvp, ep, s, nvp, mode_override, L.lowrank ? prec : H2_PREC_FP64);
-          if (r != H2_OK) return r;
-          HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
-          HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
-          float ms = 0.0f;
-          HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-          if (rep > 0) tsum += ms;  // the first repetition warms up
+      for (int64_t g : grids)
+        for (int remap = 0; remap < 2; ++remap) {
+          if (g != 0 && g >= L.row_count) continue;
+          Launch T = L;
+          T.kcp[pi] = kc;
+          T.gridp[pi] = g;
+          T.remapp[pi] = remap;
+          float tsum = 0.0f;
+          for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
+            int r = run_launch(h, w, T, nvp, ep, s, nvp, mode_override, L.lowrank ? prec : H2_PREC_FP64);
+            if (r != H2_OK) return r;
+            HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
+            HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (rep > 0) tsum += ms;  // the first repetition warms up
+          }
+          if (tsum < best) {
+            best = tsum;
+            best_kc = kc;
+            best_grid = g;
+            best_remap = remap;
+          }
         }
-        if (tsum < best) {
-          best = tsum;
-          best_kc = kc;
-          best_grid = g;
-        }
-      }
     }
     L.kcp[pi] = best_kc;
     L.gridp[pi] = best_grid;
+    L.remapp[pi] = best_remap;
+    if (tbest) *tbest = best;
     return H2_OK;
   };
   Plan& plan = h->planN;
-  for (auto* v : {&plan.up, &plan.couple, &plan.down, &plan.dense, &plan.dense2})
-    for (Launch& L : *v)
-      if ((rc = tune_one(L, -1)) != H2_OK) break;
-  if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM);
+  auto tune_list = [&](std::vector<Launch>& v, float* total) -> int {
+    *total = 0.0f;
+    for (Launch& L : v) {
+      float t = 0.0f;
+      const int r = tune_one(L, -1, &t);
+      if (r != H2_OK) return r;
+      *total += t;
+    }
+    return H2_OK;
+  };
+  float t_up = 0, t_down = 0, tc = 0, tcl = 0, td1 = 0, td2 = 0, tl1 = 0, tl2 = 0;
+  rc = tune_list(plan.up, &t_up);
+  if (rc == H2_OK) rc = tune_list(plan.down, &t_down);
+  if (rc == H2_OK) rc = tune_list(plan.couple, &tc);
+  if (rc == H2_OK) rc = tune_list(plan.couple_loc, &tcl);
+  if (rc == H2_OK) rc = tune_list(plan.dense, &td1);
+  if (rc == H2_OK) rc = tune_list(plan.dense2, &td2);
+  if (rc == H2_OK) rc = tune_list(plan.dense_loc, &tl1);
+  if (rc == H2_OK) rc = tune_list(plan.dense2_loc, &tl2);
+  if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM, nullptr);
+  if (rc == H2_OK) {
+    h->loc_couple[prec] = tcl < tc;
+    h->loc_dense[prec] = tl1 + tl2 < td1 + td2;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;

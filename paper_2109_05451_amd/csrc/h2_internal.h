@@ -48,6 +48,7 @@ struct Parsed {
 };
 
 // Parse and validate; returns H2_OK, H2_EFORMAT, H2_EUNSUPPORTED, H2_ENOMEM.
+// Reads the header and the index sections only (bytes before U).
 int parse(const uint8_t* buf, int64_t len, Parsed* p);
 
 // One output row-block processed by one workgroup: out[out_off + a + out_ld*v]
@@ -109,6 +110,7 @@ struct Launch {
   // by h2_tune
   int kcp[3] = {64, 64, 64};
   int64_t gridp[3] = {0, 0, 0};
+  int remapp[3] = {0, 0, 0};  // XCD-aware row ranges
 };
 
 // The launch sequence of one operation (op 'N' or 'T').
@@ -118,6 +120,9 @@ struct Plan {
   std::vector<Launch> down;    // transfer levels 1..q
   std::vector<Launch> dense;   // dense leaf blocks, first half (side stream, beside the upsweep)
   std::vector<Launch> dense2;  // second half (side stream, beside the downsweep and leaf expansion)
+  // the same rows in tree order (neighbouring rows share input segments), for
+  // the multi-vector path when the tuner finds it faster
+  std::vector<Launch> couple_loc, dense_loc, dense2_loc;
   Launch out;                  // leaf expansion + dense partial + alpha/beta update
 };
 
@@ -208,6 +213,11 @@ int check_gemv_args(h2_op_s* h, char op, double alpha, const double* X, int64_t 
                     int64_t ldy, int prec, bool* trans);
 void ws_destroy(Workspace* w);
 int64_t ws_bytes(int64_t n, int64_t H, int64_t cap);
+// A new handle on `device` from a representation of `len` bytes whose first
+// bytes are at `buf`.  With d_dense == nullptr the whole representation is in
+// `buf`; otherwise `buf` holds the bytes before the dense section only and
+// the dense blocks are copied from device memory at d_dense (same device).
+int load_handle(const uint8_t* buf, int64_t len, int device, const double* d_dense, h2_handle* out);
 
 }  // namespace h2
 
@@ -230,11 +240,18 @@ struct h2_op_s {
   int32_t* d_perm = nullptr;
   int32_t* d_pinv = nullptr;  // original index -> tree position
   bool mfma_ok = true;        // every op-'N' launch fits the MFMA row kernel
+  bool loc_couple[3] = {false, false, false};  // per precision: tree-ordered coupling rows (h2_tune)
+  bool loc_dense[3] = {false, false, false};   // per precision: tree-ordered dense rows
   h2::RowTables rt;           // streaming rows of both plans
   h2::RowTables wide;         // rows too wide for the tabled kernel
   h2::GatherTables gt;        // transposed rows of the 'T' plan
   h2::Plan planN, planT;
   int64_t index_bytes = 0;
+  // the serialized header and index sections (bytes before U), 8-byte aligned,
+  // and the representation's total size: the host view of the structure
+  // (export, recompression)
+  std::vector<uint64_t> prefix;
+  int64_t prefix_len = 0, file_len = 0;
   h2::Workspace ws;  // the handle's own workspace (h2_gemv), allocated on first use
   // profiling
   bool profiling = false;
@@ -256,7 +273,7 @@ hipError_t launch_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend
 template <typename T>
 hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int kc = 64, int64_t grid = 0);
+                            hipStream_t s, int kc = 64, int64_t grid = 0, int remap = 0);
 
 // One operator's part of a batched call, as the batched permutation kernels see it.
 struct BatchItem {
@@ -275,7 +292,8 @@ hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s
 // BF16 path (data: __bf16, rows stored row-major; see the kernel file)
 hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                                  const void* data, const void* in, bool in16, int64_t ldb, void* out, bool out16,
-                                 int64_t ldo, int nvp, int mode, int max_rows, hipStream_t s, int64_t grid = 0);
+                                 int64_t ldo, int nvp, int mode, int max_rows, hipStream_t s, int64_t grid = 0,
+                                 int remap = 0);
 hipError_t launch_rows_to_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const double* src,
                                void* dst, hipStream_t s);
 hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pinv, double* xt, int64_t n, int nv,

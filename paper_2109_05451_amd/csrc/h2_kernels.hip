@@ -15,6 +15,8 @@
 // independent) and the dense leaf rows are all row lists of one streaming
 // kernel; only the epilogue differs (store, accumulate, or the final
 // permuted alpha/beta update).
+#include <algorithm>
+
 #include "h2_internal.h"
 
 namespace h2 {
@@ -262,14 +264,22 @@ __global__ __launch_bounds__(kT) void k_rows_mfma(const RowDesc* __restrict__ ro
                                                   const int32_t* __restrict__ colend,
                                                   const int64_t* __restrict__ in_off,
                                                   const T* __restrict__ data, const double* in, double* out,
-                                                  int mode) {
+                                                  int mode, int remap) {
   typedef typename MfmaAcc<T>::t CT;
   constexpr int NVP = 16 * NT;
   __shared__ T bs[KC * NVP];
   __shared__ int32_t s_end[kNbMax];
   __shared__ int64_t s_in[kNbMax];
   __shared__ int64_t s_src[KC];  // input row of each column of the chunk
-  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+  // rows by workgroup: plain grid-stride, or (remap) each XCD (workgroups
+  // b with the same b % 8) takes one contiguous eighth of the rows, so that
+  // neighbouring rows, which share input segments, meet in the same L2
+  const int64_t per = remap ? (nrows + 7) / 8 : nrows;
+  const int64_t xcd = remap ? blockIdx.x % 8 : 0;
+  const int64_t step = remap ? gridDim.x / 8 : gridDim.x;
+  for (int64_t jr = remap ? blockIdx.x / 8 : blockIdx.x; jr < per; jr += step) {
+    const int64_t ri = xcd * per + jr;
+    if (ri >= nrows) break;
   __syncthreads();  // LDS of the previous row fully consumed
   const RowDesc R = rows[ri];
   const int m = R.nrows;
@@ -435,6 +445,17 @@ __global__ __launch_bounds__(kT) void k_rows_t(const RowDesc* __restrict__ rows,
 
 inline unsigned grid1d(int64_t total, int threads) { return (unsigned)((total + threads - 1) / threads); }
 
+// Workgroups of a row launch: `grid` (0 = one per row) capped at the rows;
+// with the XCD remap a multiple of 8 covering eight equal row ranges.
+inline int64_t grid_of_rows(int64_t nrows, int64_t grid, int remap) {
+  int64_t g = grid > 0 && grid < nrows ? grid : nrows;
+  if (remap) {
+    const int64_t per = (nrows + 7) / 8;
+    g = std::min<int64_t>((g + 7) / 8 * 8, 8 * per);
+  }
+  return g;
+}
+
 }  // namespace
 
 hipError_t launch_permute_in(const double* X, int64_t ldx, const int32_t* perm, double* xt, int64_t n, int nv,
@@ -476,11 +497,12 @@ template hipError_t launch_rows<float>(const RowDesc*, int64_t, const int32_t*, 
 template <typename T>
 hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int kc, int64_t grid) {
+                            hipStream_t s, int kc, int64_t grid, int remap) {
   if (nrows == 0) return hipSuccess;
-  const dim3 g((unsigned)(grid > 0 && grid < nrows ? grid : nrows)), block(kT);
-#define H2_MFMA3(NT, MAXT, KC) \
-  hipLaunchKernelGGL((k_rows_mfma<T, NT, MAXT, KC>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, mode)
+  const dim3 g((unsigned)grid_of_rows(nrows, grid, remap)), block(kT);
+#define H2_MFMA3(NT, MAXT, KC)                                                                                   \
+  hipLaunchKernelGGL((k_rows_mfma<T, NT, MAXT, KC>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, \
+                     mode, remap)
 #define H2_MFMA(NT)                                     \
   do {                                                  \
     if (max_rows <= 64) {                               \
@@ -503,9 +525,9 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
   return hipGetLastError();
 }
 template hipError_t launch_rows_mfma<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
-                                             const double*, double*, int, int, int, hipStream_t, int, int64_t);
+                                             const double*, double*, int, int, int, hipStream_t, int, int64_t, int);
 template hipError_t launch_rows_mfma<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
-                                            const double*, double*, int, int, int, hipStream_t, int, int64_t);
+                                            const double*, double*, int, int, int, hipStream_t, int, int64_t, int);
 
 // Batched input permutation: operator blockIdx.y, original index j.  Rows
 // of the workspace arena are row-major with nvp vectors; padding vectors,
@@ -561,7 +583,8 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict
                                                        const int32_t* __restrict__ colend,
                                                        const int64_t* __restrict__ in_off,
                                                        const __bf16* __restrict__ data, const void* in,
-                                                       int64_t ldb, void* out, int64_t ldo, int mode) {
+                                                       int64_t ldb, void* out, int64_t ldo, int mode,
+                                                       int remap) {
   constexpr int NVP = 16 * NT;
   constexpr int KC = 64;       // columns per LDS chunk (two k-steps of 32)
   constexpr int KCP = KC + 8;  // padded LDS row: 144 bytes, so 16 rows hit 16 distinct 16-byte bank groups
@@ -569,7 +592,15 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_bf16(const RowDesc* __restrict
   __shared__ int32_t s_end[kNbMax];
   __shared__ int64_t s_in[kNbMax];
   __shared__ int64_t s_src[KC];
-  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+  // rows by workgroup: plain grid-stride, or (remap) each XCD (workgroups
+  // b with the same b % 8) takes one contiguous eighth of the rows, so that
+  // neighbouring rows, which share input segments, meet in the same L2
+  const int64_t per = remap ? (nrows + 7) / 8 : nrows;
+  const int64_t xcd = remap ? blockIdx.x % 8 : 0;
+  const int64_t step = remap ? gridDim.x / 8 : gridDim.x;
+  for (int64_t jr = remap ? blockIdx.x / 8 : blockIdx.x; jr < per; jr += step) {
+    const int64_t ri = xcd * per + jr;
+    if (ri >= nrows) break;
     __syncthreads();
     const RowDesc R = rows[ri];
     const int m = R.nrows;
@@ -715,15 +746,16 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 
 hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                                  const void* data, const void* in, bool in16, int64_t ldb, void* out, bool out16,
-                                 int64_t ldo, int nvp, int mode, int max_rows, hipStream_t s, int64_t grid) {
+                                 int64_t ldo, int nvp, int mode, int max_rows, hipStream_t s, int64_t grid,
+                                 int remap) {
   if (nrows == 0) return hipSuccess;
   if (out16 && mode != MODE_STORE) return hipErrorInvalidValue;
   if ((in16 || out16) && (ldb % 8 != 0 || ldo % 8 != 0)) return hipErrorInvalidValue;
-  const dim3 g((unsigned)(grid > 0 && grid < nrows ? grid : nrows)), block(kT);
+  const dim3 g((unsigned)grid_of_rows(nrows, grid, remap)), block(kT);
   const __bf16* d = static_cast<const __bf16*>(data);
 #define H2_BF4(NT, MAXT, BS, O16) \
   hipLaunchKernelGGL((k_rows_mfma_bf16<NT, MAXT, BS, O16>), g, block, 0, s, rows, nrows, colend, in_off, d, in, \
-                     ldb, out, ldo, mode)
+                     ldb, out, ldo, mode, remap)
 #define H2_BF2(NT, MAXT)                                              \
   do {                                                                \
     if (in16) {                                                       \
