@@ -75,6 +75,9 @@ def time_gpu(g, X, Y, nv, steps, warmup, torch, precision="fp64"):
     if precision != "fp64":
         g.prepare(precision)
     g.tune(nv, precision, stream.cuda_stream)
+    if nv > 4 or precision == "bf16":
+        print("# tuned plan (" + precision + "):\n# " + g.plan_info().strip().replace("\n", "\n# "),
+              file=sys.stderr, flush=True)
     for _ in range(warmup):
         g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream.cuda_stream, precision)
     torch.cuda.synchronize()

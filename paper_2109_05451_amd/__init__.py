@@ -20,7 +20,7 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve", "h2_tune",
-           "h2_compress", "h2_export", "h2_ranks",
+           "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set",
            "h2_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
@@ -110,6 +110,10 @@ def load_library(path: str = LIB_PATH):
     lib.h2_export.restype = ci
     lib.h2_ranks.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i64]
     lib.h2_ranks.restype = ci
+    lib.h2_plan_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.h2_plan_info.restype = ci
+    lib.h2_tune_set.argtypes = [vp, ci, ci, i64, ci, ci]
+    lib.h2_tune_set.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
     lib.h2_stats.restype = ci
     lib.h2_n.argtypes = [vp]
@@ -210,6 +214,21 @@ class H2Operator:
         buf = np.zeros(need.value // 8 + 1, dtype=np.uint64).view(np.uint8)[:need.value]
         _check(lib.h2_export(self._h, buf.ctypes.data, buf.size, ctypes.byref(need)))
         return buf
+
+    def tune_set(self, precision: str = "fp64", kc: int = 64, grid: int = 0, xcd: bool = False,
+                 tree_order: int = 0):
+        """Fixed multi-vector launch parameters for every launch (see h2_tune_set)."""
+        _check(load_library().h2_tune_set(self._h, PRECISIONS[precision], kc, grid, 1 if xcd else 0,
+                                          int(tree_order)))
+
+    def plan_info(self) -> str:
+        """Text description of the launch plan and its tuned parameters."""
+        lib = load_library()
+        need = ctypes.c_size_t()
+        _check(lib.h2_plan_info(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.h2_plan_info(self._h, buf, need.value, ctypes.byref(need)))
+        return buf.value.decode()
 
     def ranks(self):
         """Row and column ranks per level."""

@@ -3,6 +3,7 @@
 // done here at load time because the structure is static), the product
 // h2_gemv, and the helpers declared in include/h2.h.
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -491,10 +492,11 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   const Plan& plan = trans ? h->planT : h->planN;
   // tree-ordered coupling / dense rows on the multi-vector path when tuned so
   const int pidx = prec == H2_PREC_FP32 ? 1 : prec == H2_PREC_BF16 ? 2 : 0;
-  const bool lc = !trans && nvp > 0 && h->loc_couple[pidx], ld = !trans && nvp > 0 && h->loc_dense[pidx];
-  const std::vector<Launch>& couple = lc ? plan.couple_loc : plan.couple;
-  const std::vector<Launch>& dense1 = ld ? plan.dense_loc : plan.dense;
-  const std::vector<Launch>& dense2 = ld ? plan.dense2_loc : plan.dense2;
+  const int cm = (!trans && nvp > 0) ? h->couple_mode[pidx] : 0;
+  const int dm = (!trans && nvp > 0) ? h->dense_mode[pidx] : 0;
+  const std::vector<Launch>& couple = cm == 1 ? plan.couple_loc : plan.couple;
+  const std::vector<Launch>& dense1 = dm == 1 ? plan.dense_loc : plan.dense;
+  const std::vector<Launch>& dense2 = dm == 1 ? plan.dense2_loc : plan.dense2;
   std::array<hipEvent_t, 11>* ev = nullptr;
   if (h->profiling && &w == &h->ws) {
     if (h->ev_used == h->ev_pool.size()) {
@@ -755,16 +757,21 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   // best candidate of one launch; its time (ms, two timed runs) in *tbest
   auto tune_one = [&](Launch& L, int mode_override, float* tbest) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
-    const int kcs[2] = {32, 64};
+    const int kcs[6] = {32, 64, 0, 1, 2, 3};  // 0: pipelined, 1-3: balanced (64 vectors only)
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
     int best_kc = L.kcp[pi], best_remap = L.remapp[pi];
     int64_t best_grid = L.gridp[pi];
     for (int kc : kcs) {
       if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
+      if (kc >= 0 && kc <= 3 && nvp != 64) continue;
+      if (kc >= 1 && kc <= 3 && L.max_rows > 64) continue;
       for (int64_t g : grids)
         for (int remap = 0; remap < 2; ++remap) {
           if (g != 0 && g >= L.row_count) continue;
+          // the dense rows run beside the sweeps: a persistent grid would hold
+          // every CU slot and starve them, so they keep one workgroup per row
+          if (g != 0 && !L.lowrank) continue;
           Launch T = L;
           T.kcp[pi] = kc;
           T.gridp[pi] = g;
@@ -791,6 +798,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     L.kcp[pi] = best_kc;
     L.gridp[pi] = best_grid;
     L.remapp[pi] = best_remap;
+    L.tuned_ms[pi] = best / 2;
     if (tbest) *tbest = best;
     return H2_OK;
   };
@@ -816,12 +824,91 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if (rc == H2_OK) rc = tune_list(plan.dense2_loc, &tl2);
   if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM, nullptr);
   if (rc == H2_OK) {
-    h->loc_couple[prec] = tcl < tc;
-    h->loc_dense[prec] = tl1 + tl2 < td1 + td2;
+    h->couple_mode[prec] = tcl < tc ? 1 : 0;
+    h->dense_mode[prec] = tl1 + tl2 < td1 + td2 ? 1 : 0;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;
+}
+
+int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_order) {
+  if (!h) { set_error("null handle"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_BF16) {
+    set_error("unknown precision");
+    return H2_EINVAL;
+  }
+  if (!(kc >= 0 && kc <= 3) && kc != 32 && kc != 64) {
+    set_error("kc must be 0, 1, 2, 3, 32 or 64");
+    return H2_EINVAL;
+  }
+  if (prec == H2_PREC_BF16 && kc != 64) { set_error("the BF16 kernel has kc 64 only"); return H2_EINVAL; }
+  if (grid < 0) { set_error("grid < 0"); return H2_EINVAL; }
+  DeviceGuard guard(h->device);
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  Plan& P = h->planN;
+  for (auto* v : {&P.up, &P.couple, &P.down, &P.couple_loc})
+    for (Launch& L : *v) {
+      L.kcp[prec] = kc;
+      L.gridp[prec] = grid;
+      L.remapp[prec] = xcd ? 1 : 0;
+    }
+  P.out.kcp[prec] = kc;
+  P.out.gridp[prec] = grid;
+  P.out.remapp[prec] = xcd ? 1 : 0;
+  if (prec == H2_PREC_FP64 || kc != 0)  // the dense rows are always FP64
+    for (auto* v : {&P.dense, &P.dense2, &P.dense_loc, &P.dense2_loc})
+      for (Launch& L : *v) {
+        L.kcp[H2_PREC_FP64] = prec == H2_PREC_BF16 ? 64 : kc;
+        L.gridp[H2_PREC_FP64] = grid;
+        L.remapp[H2_PREC_FP64] = xcd ? 1 : 0;
+      }
+  h->couple_mode[prec] = tree_order != 0 ? 1 : 0;
+  h->dense_mode[prec] = tree_order != 0 ? 1 : 0;
+  return H2_OK;
+}
+
+int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
+  if (!h || !needed) { set_error("null handle or size output"); return H2_EINVAL; }
+  std::string t;
+  char line[256];
+  const char* pn[3] = {"fp64", "fp32", "bf16"};
+  for (int p = 0; p < 3; ++p) {
+    const char* cmn[2] = {"longest first", "tree order"};
+    std::snprintf(line, sizeof line, "%s: coupling rows %s, dense rows %s\n", pn[p], cmn[h->couple_mode[p]],
+                  cmn[h->dense_mode[p]]);
+    t += line;
+  }
+  auto dump = [&](const char* phase, const std::vector<Launch>& v) {
+    for (const Launch& L : v) {
+      std::snprintf(line, sizeof line, "%s rows=%lld max_rows=%d kind=%d", phase, (long long)L.row_count, L.max_rows,
+                    L.kind);
+      t += line;
+      for (int p = 0; p < 3; ++p) {
+        std::snprintf(line, sizeof line, " | %s kc=%d grid=%lld xcd=%d %.3fms", pn[p], L.kcp[p],
+                      (long long)L.gridp[p], L.remapp[p], L.tuned_ms[p]);
+        t += line;
+      }
+      t += "\n";
+    }
+  };
+  const Plan& P = h->planN;
+  dump("up", P.up);
+  dump("couple", P.couple);
+  dump("couple_tree", P.couple_loc);
+  dump("down", P.down);
+  dump("dense1", P.dense);
+  dump("dense2", P.dense2);
+  dump("dense1_tree", P.dense_loc);
+  dump("dense2_tree", P.dense2_loc);
+  dump("out", std::vector<Launch>{P.out});
+  *needed = t.size() + 1;
+  if (buf && cap > 0) {
+    const size_t c = std::min(cap - 1, t.size());
+    std::memcpy(buf, t.data(), c);
+    buf[c] = 0;
+  }
+  return H2_OK;
 }
 
 int h2_stats(h2_handle h, h2_stats_t* st) {

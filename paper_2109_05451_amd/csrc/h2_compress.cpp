@@ -66,10 +66,23 @@ class Arena {
     CK(hipMemsetAsync(*out, 0, bytes, s), "hipMemsetAsync(compression)");
     return H2_OK;
   }
-  // asynchronous upload of a copy of v that the arena keeps until it is destroyed
+  // asynchronous upload of a copy of v that the arena keeps until it is
+  // destroyed; small uploads are carved from 16 MiB device chunks
   template <class T>
   int upload(const std::vector<T>& v, T** out, hipStream_t s) {
-    RC(alloc(out, (int64_t)v.size(), s));
+    const size_t bytes = (sizeof(T) * std::max<size_t>(v.size(), 1) + 255) / 256 * 256;
+    if (bytes > kChunk) {
+      RC(alloc(out, (int64_t)v.size(), s));
+    } else {
+      if (!chunk_ || used_ + bytes > kChunk) {
+        uint8_t* c = nullptr;
+        RC(alloc(&c, (int64_t)kChunk, s));
+        chunk_ = c;
+        used_ = 0;
+      }
+      *out = reinterpret_cast<T*>(chunk_ + used_);
+      used_ += bytes;
+    }
     if (v.empty()) return H2_OK;
     host_.emplace_back(reinterpret_cast<const uint8_t*>(v.data()),
                        reinterpret_cast<const uint8_t*>(v.data()) + sizeof(T) * v.size());
@@ -94,6 +107,9 @@ class Arena {
   std::vector<void*> ptrs_;
   std::vector<std::pair<uintptr_t, uintptr_t>> regions_;
   std::vector<std::vector<uint8_t>> host_;
+  static constexpr size_t kChunk = size_t(16) << 20;
+  uint8_t* chunk_ = nullptr;
+  size_t used_ = 0;
 };
 
 int oob(const char* what) {
@@ -143,6 +159,16 @@ struct Ctx {
   double* So = nullptr;          // orthogonalized coupling blocks
   int64_t m(int64_t c) const { return P.hi[c] - P.lo[c]; }
 };
+
+int launch_eigs(Ctx& C, const std::vector<EigTask>& tasks) {
+  if (tasks.empty()) return H2_OK;
+  int nmax = 0;
+  for (const EigTask& t : tasks) nmax = std::max(nmax, t.n);
+  EigTask* d = nullptr;
+  RC(C.ar.upload(tasks, &d, C.s));
+  CK(launch_eig(d, (int64_t)tasks.size(), nmax, C.s), "eigensolver");
+  return H2_OK;
+}
 
 template <class T>
 int launch_tasks(Ctx& C, const std::vector<T>& tasks, hipError_t (*fn)(const T*, int64_t, hipStream_t)) {
@@ -353,7 +379,7 @@ int truncate(Ctx& C, Tree& X, double tau) {
       leaf_counts.push_back(CountTask{X.lam + C.nk[t], (int32_t)kq, (int32_t)t});
     }
     RC(launch_tasks(C, mt, launch_mask_gram));
-    RC(launch_tasks(C, et, launch_eig));
+    RC(launch_eigs(C, et));
   }
   double sref2 = 0.0;
   if (!leaf_counts.empty()) {
@@ -436,7 +462,7 @@ int truncate(Ctx& C, Tree& X, double tau) {
       sc.push_back(ScaleTask{X.Z + C.nk2[p], kp, X.lam + C.nk[p], (int32_t)kp, (int32_t)kp, (int32_t)p, 0});
     }
     RC(launch_gemm_tasks(C, g1, p1));
-    RC(launch_tasks(C, e1, launch_eig));
+    RC(launch_eigs(C, e1));
     if (!e1.empty()) {
       EigTask* de = nullptr;
       double** dout = nullptr;
@@ -448,7 +474,7 @@ int truncate(Ctx& C, Tree& X, double tau) {
     }
     RC(launch_gemm_tasks(C, g2, p2));
     RC(launch_gemm_tasks(C, g3, p3));
-    RC(launch_tasks(C, e2, launch_eig));
+    RC(launch_eigs(C, e2));
     if (!cnt.empty()) {
       CountTask* d = nullptr;
       RC(C.ar.upload(cnt, &d, C.s));

@@ -247,37 +247,51 @@ __global__ __launch_bounds__(kCT) void k_triple(const TripleTask* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi for a symmetric n x n matrix (n <= 64): rounds of
-// n'/2 disjoint rotations (n' = n rounded up to even; the padding index only
-// meets identity rotations), tournament ordering, n' - 1 rounds per sweep,
-// until a sweep rotates nothing.  Rotation (c, s) from the 2 x 2 symmetric
-// Schur decomposition zeroes A[p][q] in J^T A J, J = [[c, s], [-s, c]].
-__global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) {
-  constexpr int N = kMaxCompressRank, LD = N + 1;
-  __shared__ double sA[N * LD];
-  __shared__ double sV[N * LD];
-  __shared__ double rc[N / 2], rs[N / 2];
-  __shared__ int rp[N / 2], rq[N / 2];
-  __shared__ int s_rot;
-  __shared__ double s_lam[N];
-  const EigTask T = tasks[blockIdx.x];
-  const int n = T.n, tid = threadIdx.x;
+// Parallel cyclic Jacobi for symmetric n x n matrices (n <= N), one
+// wavefront per matrix (W wavefronts, so W matrices, per workgroup; the
+// matrix and its eigenvectors live in LDS and only lanes of one wavefront
+// touch them, so phases are ordered by wavefront-scope fences).  Each round
+// applies n'/2 disjoint rotations (n' = n rounded up to even; the padding
+// index only meets identity rotations) in tournament order, n' - 1 rounds
+// per sweep, until a sweep rotates nothing.  Rotation (c, s) from the 2 x 2
+// symmetric Schur decomposition zeroes A[p][q] in J^T A J, J = [[c, s], [-s, c]].
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int N, int W>
+__global__ __launch_bounds__(64 * W) void k_eig(const EigTask* __restrict__ tasks, int64_t ntasks) {
+  constexpr int LD = N + 1;
+  __shared__ double sA_all[W][N * LD];
+  __shared__ double sV_all[W][N * LD];
+  __shared__ double rc_all[W][N / 2], rs_all[W][N / 2];
+  __shared__ int rp_all[W][N / 2], rq_all[W][N / 2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t ti = (int64_t)blockIdx.x * W + wv;
+  if (ti >= ntasks) return;  // whole wavefront leaves; no workgroup barrier below
+  double* sA = sA_all[wv];
+  double* sV = sV_all[wv];
+  double* rc = rc_all[wv];
+  double* rs = rs_all[wv];
+  int* rp = rp_all[wv];
+  int* rq = rq_all[wv];
+  const EigTask T = tasks[ti];
+  const int n = T.n;
   const int np = (n + 1) & ~1, half = np / 2;
-  for (int e = tid; e < n * n; e += kCT) {
+  for (int e = lane; e < n * n; e += 64) {
     const int j = e / n, i = e - j * n;
-    // symmetrize (the inputs are symmetric up to rounding)
     sA[i * LD + j] = 0.5 * (T.G[i + (int64_t)j * T.ldg] + T.G[j + (int64_t)i * T.ldg]);
     sV[i * LD + j] = i == j ? 1.0 : 0.0;
   }
-  __syncthreads();
+  wave_sync();
   for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
+    bool rot = false;
     for (int round = 0; round < np - 1; ++round) {
-      if (tid < half) {
+      for (int k = lane; k < half; k += 64) {
         int p, q;
-        if (tid == 0) { p = round; q = np - 1; }
-        else { p = (round + tid) % (np - 1); q = (round - tid + (np - 1)) % (np - 1); }
+        if (k == 0) { p = round; q = np - 1; }
+        else { p = (round + k) % (np - 1); q = (round - k + (np - 1)) % (np - 1); }
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
@@ -287,14 +301,13 @@ __global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) 
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
-            s_rot = 1;
+            rot = true;
           }
         }
-        rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s;
+        rp[k] = p; rq[k] = q; rc[k] = c; rs[k] = s;
       }
-      __syncthreads();
-      // rows: p' = c p - s q, q' = s p + c q
-      for (int e = tid; e < half * n; e += kCT) {
+      wave_sync();
+      for (int e = lane; e < half * n; e += 64) {
         const int k = e / n, j = e - k * n;
         const int p = rp[k], q = rq[k];
         if (q < n && rs[k] != 0.0) {
@@ -304,9 +317,8 @@ __global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) 
           sA[q * LD + j] = s * ap + c * aq;
         }
       }
-      __syncthreads();
-      // columns of A and V: p'' = c p - s q, q'' = s p + c q
-      for (int e = tid; e < half * n; e += kCT) {
+      wave_sync();
+      for (int e = lane; e < half * n; e += 64) {
         const int k = e / n, i = e - k * n;
         const int p = rp[k], q = rq[k];
         if (q < n && rs[k] != 0.0) {
@@ -319,18 +331,18 @@ __global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) 
           sV[i * LD + q] = s * vp + c * vq;
         }
       }
-      __syncthreads();
+      wave_sync();
     }
-    if (s_rot == 0) break;
-    __syncthreads();
+    if (!__any(rot)) break;
   }
   // descending order (ties by index)
-  for (int i = tid; i < n; i += kCT) s_lam[i] = sA[i * LD + i];
-  __syncthreads();
-  for (int i = tid; i < n; i += kCT) {
-    const double li = s_lam[i];
+  for (int i = lane; i < n; i += 64) {
+    const double li = sA[i * LD + i];
     int rank = 0;
-    for (int j = 0; j < n; ++j) rank += (s_lam[j] > li) || (s_lam[j] == li && j < i);
+    for (int j = 0; j < n; ++j) {
+      const double lj = sA[j * LD + j];
+      rank += (lj > li) || (lj == li && j < i);
+    }
     T.lam[rank] = li;
     for (int row = 0; row < n; ++row) T.Z[row + (int64_t)rank * T.ldz] = sV[row * LD + i];
   }
@@ -439,9 +451,16 @@ hipError_t launch_triple(const TripleTask* t, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_triple, grid_of(n), dim3(kCT), 0, s, t);
   return hipGetLastError();
 }
-hipError_t launch_eig(const EigTask* t, int64_t n, hipStream_t s) {
+hipError_t launch_eig(const EigTask* t, int64_t n, int nmax, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eig, grid_of(n), dim3(kCT), 0, s, t);
+  if (nmax <= 32)
+    hipLaunchKernelGGL((k_eig<32, 4>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, n);
+  else if (nmax <= 48)
+    hipLaunchKernelGGL((k_eig<48, 4>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, n);
+  else if (nmax <= kMaxCompressRank)
+    hipLaunchKernelGGL((k_eig<64, 2>), dim3((unsigned)((n + 1) / 2)), dim3(128), 0, s, t, n);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 hipError_t launch_mask_gram(const MaskTask* t, int64_t n, hipStream_t s) {

@@ -111,6 +111,7 @@ struct Launch {
   int kcp[3] = {64, 64, 64};
   int64_t gridp[3] = {0, 0, 0};
   int remapp[3] = {0, 0, 0};  // XCD-aware row ranges
+  float tuned_ms[3] = {0, 0, 0};  // time of the chosen setting when tuned (two runs)
 };
 
 // The launch sequence of one operation (op 'N' or 'T').
@@ -240,8 +241,8 @@ struct h2_op_s {
   int32_t* d_perm = nullptr;
   int32_t* d_pinv = nullptr;  // original index -> tree position
   bool mfma_ok = true;        // every op-'N' launch fits the MFMA row kernel
-  bool loc_couple[3] = {false, false, false};  // per precision: tree-ordered coupling rows (h2_tune)
-  bool loc_dense[3] = {false, false, false};   // per precision: tree-ordered dense rows
+  int couple_mode[3] = {0, 0, 0};  // per precision: 0 longest first, 1 tree order (h2_tune)
+  int dense_mode[3] = {0, 0, 0};   // per precision: 0 longest first, 1 tree order (h2_tune)
   h2::RowTables rt;           // streaming rows of both plans
   h2::RowTables wide;         // rows too wide for the tabled kernel
   h2::GatherTables gt;        // transposed rows of the 'T' plan

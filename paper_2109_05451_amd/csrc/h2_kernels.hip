@@ -222,23 +222,52 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // X~ (tree order, row-major NVP) from X (original order, column-major):
 // thread per original index j reads X[j, v] (coalesced over j) and writes
 // the row of tree position pinv[j].
-__global__ void k_permute_in_rm(const double* __restrict__ X, int64_t ldx, const int32_t* __restrict__ pinv,
-                                double* __restrict__ xt, int64_t n, int nv, int nvp) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double* row = xt + (int64_t)pinv[j] * nvp;
-  for (int v = 0; v < nvp; ++v) row[v] = v < nv ? X[j + ldx * v] : 0.0;
+// Permutations of the multi-vector path through an LDS tile of 64 points x
+// nvp vectors, so that both the column-major side (64 consecutive points of
+// one vector) and the tree-ordered side (one point's nvp vectors, contiguous)
+// are accessed with coalesced loads and stores.
+constexpr int kPermTile = 64;
+
+// xt[pinv[j], v] = X[j, v] for v < nv, 0 for nv <= v < nvp.
+__global__ __launch_bounds__(256) void k_permute_in_rm(const double* __restrict__ X, int64_t ldx,
+                                                       const int32_t* __restrict__ pinv, double* __restrict__ xt,
+                                                       int64_t n, int nv, int nvp) {
+  __shared__ double tile[kPermTile * (kPassVectorsMfma + 1)];
+  constexpr int LD = kPassVectorsMfma + 1;
+  const int64_t j0 = blockIdx.x * (int64_t)kPermTile;
+  const int rows = (int)min<int64_t>(kPermTile, n - j0);
+  for (int e = threadIdx.x; e < kPermTile * nvp; e += blockDim.x) {
+    const int v = e / kPermTile, jj = e - v * kPermTile;
+    if (jj < rows) tile[jj * LD + v] = v < nv ? X[j0 + jj + ldx * v] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kPermTile * nvp; e += blockDim.x) {
+    const int jj = e / nvp, v = e - jj * nvp;
+    if (jj < rows) xt[(int64_t)pinv[j0 + jj] * nvp + v] = tile[jj * LD + v];
+  }
 }
 
-// Y[j, v] = alpha * Z[pinv[j], v] + beta * Y[j, v] (Z row-major NVP, tree order).
-__global__ void k_permute_out_rm(const double* __restrict__ Z, const int32_t* __restrict__ pinv, double alpha,
-                                 double beta, double* __restrict__ Y, int64_t ldy, int64_t n, int nv, int nvp) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double* row = Z + (int64_t)pinv[j] * nvp;
-  for (int v = 0; v < nv; ++v) {
-    double* y = Y + j + ldy * v;
-    *y = beta == 0.0 ? alpha * row[v] : alpha * row[v] + beta * *y;
+// Y[j, v] = alpha * Z[pinv[j], v] + beta * Y[j, v] (Z row-major nvp, tree order).
+__global__ __launch_bounds__(256) void k_permute_out_rm(const double* __restrict__ Z,
+                                                        const int32_t* __restrict__ pinv, double alpha, double beta,
+                                                        double* __restrict__ Y, int64_t ldy, int64_t n, int nv,
+                                                        int nvp) {
+  __shared__ double tile[kPermTile * (kPassVectorsMfma + 1)];
+  constexpr int LD = kPassVectorsMfma + 1;
+  const int64_t j0 = blockIdx.x * (int64_t)kPermTile;
+  const int rows = (int)min<int64_t>(kPermTile, n - j0);
+  for (int e = threadIdx.x; e < kPermTile * nvp; e += blockDim.x) {
+    const int jj = e / nvp, v = e - jj * nvp;
+    if (jj < rows && v < nv) tile[jj * LD + v] = Z[(int64_t)pinv[j0 + jj] * nvp + v];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kPermTile * nv; e += blockDim.x) {
+    const int v = e / kPermTile, jj = e - v * kPermTile;
+    if (jj < rows) {
+      double* y = Y + j0 + jj + ldy * v;
+      const double z = alpha * tile[jj * LD + v];
+      *y = beta == 0.0 ? z : z + beta * *y;
+    }
   }
 }
 
@@ -373,6 +402,280 @@ __global__ __launch_bounds__(kT) void k_rows_mfma(const RowDesc* __restrict__ ro
       }
   }
   }  // rows
+}
+
+// Software-pipelined variant for 64 vectors: the input chunk (32 columns x
+// 64 vectors) is double-buffered in LDS; the next chunk's gather is issued
+// into registers before the current chunk's MFMAs and stored after them, so
+// one barrier per chunk separates the buffers.  Wave w gathers columns
+// w, w + 4, ... of a chunk, one column (64 contiguous vectors) per load
+// instruction, and finds each column's block with a cursor that only moves
+// forward (columns increase), instead of a search per chunk.
+template <typename T, int MAXT>
+__global__ __launch_bounds__(kT) void k_rows_mfma_pipe(const RowDesc* __restrict__ rows, int64_t nrows,
+                                                       const int32_t* __restrict__ colend,
+                                                       const int64_t* __restrict__ in_off,
+                                                       const T* __restrict__ data, const double* in, double* out,
+                                                       int mode, int remap) {
+  typedef typename MfmaAcc<T>::t CT;
+  constexpr int NT = 4, NVP = 64, KC = 32, PER = KC / 4;  // PER columns per wave per chunk
+  __shared__ T bs[2][KC * NVP];
+  __shared__ int32_t s_end[kNbMax];
+  __shared__ int64_t s_in[kNbMax];
+  const int64_t per = remap ? (nrows + 7) / 8 : nrows;
+  const int64_t xcd = remap ? blockIdx.x % 8 : 0;
+  const int64_t step = remap ? gridDim.x / 8 : gridDim.x;
+  for (int64_t jr = remap ? blockIdx.x / 8 : blockIdx.x; jr < per; jr += step) {
+    const int64_t ri = xcd * per + jr;
+    if (ri >= nrows) break;
+    __syncthreads();  // LDS of the previous row fully consumed
+    const RowDesc R = rows[ri];
+    const int m = R.nrows;
+    if (m <= 0) continue;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = R.blk_end - R.blk_begin;
+    for (int i = tid; i < nb; i += kT) {
+      s_end[i] = colend[R.blk_begin + i];
+      s_in[i] = in_off[R.blk_begin + i];
+    }
+    __syncthreads();
+    const int ncols = nb > 0 ? s_end[nb - 1] : 0;
+    const int nch = (ncols + KC - 1) / KC;
+    const int mt = (m + 15) >> 4;
+    CT acc[MAXT][NT];
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = CT{0, 0, 0, 0};
+    const int arow = lane & 15, akk = lane >> 4;
+    const T* M = data + R.data_off;
+    int bw = 0;  // this wave's block cursor
+    T reg[PER];
+    auto gather = [&](int c) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int col = c * KC + wave + 4 * i;
+        T v = (T)0;
+        if (col < ncols) {
+          while (s_end[bw] <= col) ++bw;
+          const int64_t src = s_in[bw] + (col - (bw > 0 ? s_end[bw - 1] : 0));
+          v = (T)in[src * NVP + lane];
+        }
+        reg[i] = v;
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) bs[buf][(wave + 4 * i) * NVP + lane] = reg[i];
+    };
+    if (nch > 0) {
+      gather(0);
+      store(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const int buf = c & 1;
+      const int c0 = c * KC, cn = min(KC, ncols - c0);
+      if (c + 1 < nch) gather(c + 1);
+      const int nsteps = (cn + 3) >> 2;
+#pragma unroll
+      for (int ti = 0; ti < MAXT; ++ti) {
+        const int tile = wave + 4 * ti;
+        if (tile >= mt) break;
+        const int r = tile * 16 + arow;
+        const bool rok = r < m;
+        const T* Ar = M + r + (int64_t)m * c0;
+        T a[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int col = 4 * u + akk;
+          a[u] = (rok && col < cn) ? __builtin_nontemporal_load(Ar + (int64_t)m * col) : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          if (u < nsteps) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+              const T b = bs[buf][(4 * u + akk) * NVP + 16 * j + arow];
+              acc[ti][j] = mfma16x16x4(a[u], b, acc[ti][j]);
+            }
+          }
+        }
+      }
+      if (c + 1 < nch) store(buf ^ 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int tile = wave + 4 * ti;
+      if (tile >= mt) break;
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = tile * 16 + (sizeof(T) == 8 ? 4 * r + akk : 4 * akk + r);
+          if (a < m) {
+            double* o = out + (R.out_off + a) * NVP + 16 * j + arow;
+            if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
+            else *o += (double)acc[ti][j][r];
+          }
+        }
+    }
+  }
+}
+
+// Balanced variant for 64 vectors and rows of at most 64 outputs: wave w
+// owns vector tile w (16 vectors) for every 16-row tile of the row, so all
+// four waves issue MFMAs whatever the row count (a 36-row block gives each
+// wave three tiles instead of leaving one wave idle).  Both operands of a
+// chunk of KC columns go through LDS, double-buffered: the matrix chunk is a
+// contiguous m x KC slice (coalesced loads), the gathered input chunk is
+// KC x 64; the next chunk is loaded into registers before the current
+// chunk's MFMAs and stored after them, with one barrier per chunk.
+template <typename T, int KC, bool DEEP, int MT>
+__global__ __launch_bounds__(kT) void k_rows_mfma_bal(const RowDesc* __restrict__ rows, int64_t nrows,
+                                                      const int32_t* __restrict__ colend,
+                                                      const int64_t* __restrict__ in_off,
+                                                      const T* __restrict__ data, const double* in, double* out,
+                                                      int mode, int remap) {
+  typedef typename MfmaAcc<T>::t CT;
+  constexpr int NVP = 64, LDA = 68, LDB = 66;  // padded LDS rows (doubles or floats)
+  constexpr int PA = (64 * KC + kT - 1) / kT;   // matrix elements per thread per chunk (m <= 64)
+  constexpr int PB = KC / 4;                     // gathered columns per wave per chunk
+  __shared__ T sa[2][KC * LDA];
+  __shared__ T sb[2][KC * LDB];
+  __shared__ int32_t s_end[kNbMax];
+  __shared__ int64_t s_in[kNbMax];
+  const int64_t per = remap ? (nrows + 7) / 8 : nrows;
+  const int64_t xcd = remap ? blockIdx.x % 8 : 0;
+  const int64_t step = remap ? gridDim.x / 8 : gridDim.x;
+  for (int64_t jr = remap ? blockIdx.x / 8 : blockIdx.x; jr < per; jr += step) {
+    const int64_t ri = xcd * per + jr;
+    if (ri >= nrows) break;
+    __syncthreads();
+    const RowDesc R = rows[ri];
+    const int m = R.nrows;
+    if (m <= 0) continue;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = R.blk_end - R.blk_begin;
+    for (int i = tid; i < nb; i += kT) {
+      s_end[i] = colend[R.blk_begin + i];
+      s_in[i] = in_off[R.blk_begin + i];
+    }
+    __syncthreads();
+    const int ncols = nb > 0 ? s_end[nb - 1] : 0;
+    const int nch = (ncols + KC - 1) / KC;
+    const int mt = (m + 15) >> 4;
+    CT acc[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) acc[i] = CT{0, 0, 0, 0};
+    const int arow = lane & 15, akk = lane >> 4;
+    const T* M = data + R.data_off;
+    int bw = 0;
+    T ra[PA], rb[PB];
+    auto load = [&](int c, T* ra, T* rb) {
+      const int c0 = c * KC, cn = min(KC, ncols - c0);
+      const int64_t base = (int64_t)m * c0;  // the chunk is m * cn contiguous elements
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        const int e = tid + kT * i;
+        ra[i] = e < m * cn ? __builtin_nontemporal_load(M + base + e) : (T)0;
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int col = c0 + wave + 4 * i;
+        T v = (T)0;
+        if (col < ncols) {
+          while (s_end[bw] <= col) ++bw;
+          const int64_t src = s_in[bw] + (col - (bw > 0 ? s_end[bw - 1] : 0));
+          v = (T)in[src * NVP + lane];
+        }
+        rb[i] = v;
+      }
+    };
+    auto store = [&](int buf, int c, const T* ra, const T* rb) {
+      const int cn = min(KC, ncols - c * KC);
+#pragma unroll
+      for (int i = 0; i < PA; ++i) {
+        const int e = tid + kT * i;
+        if (e < m * KC) {
+          const int col = e / m, row = e - col * m;
+          sa[buf][col * LDA + row] = col < cn ? ra[i] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) sb[buf][(wave + 4 * i) * LDB + lane] = rb[i];
+    };
+    // rows m .. 16*mt of the A tiles read zeros
+    for (int e = tid; e < 2 * KC * LDA; e += kT) {
+      const int row = e % LDA;
+      if (row >= m) (&sa[0][0])[e] = (T)0;
+    }
+    auto compute = [&](int c) {
+      const int buf = c & 1;
+      const int cn = min(KC, ncols - c * KC);
+      const int nsteps = (cn + 3) >> 2;
+      const T* A = sa[buf];
+      const T* B = sb[buf];
+#pragma unroll
+      for (int u = 0; u < KC / 4; ++u) {
+        if (u < nsteps) {
+          const int k = 4 * u + akk;
+          const T b = B[k * LDB + 16 * wave + arow];
+#pragma unroll
+          for (int ti = 0; ti < MT; ++ti)
+            if (ti < mt) acc[ti] = mfma16x16x4(A[k * LDA + 16 * ti + arow], b, acc[ti]);
+        }
+      }
+    };
+    if (!DEEP) {
+      if (nch > 0) {
+        load(0, ra, rb);
+        store(0, 0, ra, rb);
+      }
+      __syncthreads();
+      for (int c = 0; c < nch; ++c) {
+        if (c + 1 < nch) load(c + 1, ra, rb);
+        compute(c);
+        if (c + 1 < nch) store((c + 1) & 1, c + 1, ra, rb);
+        __syncthreads();
+      }
+    } else {
+      // two register sets: chunk c+2 is loaded while chunk c is multiplied
+      // and chunk c+1 (loaded an iteration earlier) is stored
+      T ra2[PA], rb2[PB];
+      if (nch > 0) {
+        load(0, ra, rb);
+        store(0, 0, ra, rb);
+      }
+      if (nch > 1) load(1, ra2, rb2);
+      __syncthreads();
+      for (int c = 0; c < nch; c += 2) {
+        if (c + 2 < nch) load(c + 2, ra, rb);
+        compute(c);
+        if (c + 1 < nch) store(1, c + 1, ra2, rb2);
+        __syncthreads();
+        if (c + 1 >= nch) break;
+        if (c + 3 < nch) load(c + 3, ra2, rb2);
+        compute(c + 1);
+        if (c + 2 < nch) store(0, c + 2, ra, rb);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      if (ti >= mt) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = ti * 16 + (sizeof(T) == 8 ? 4 * r + akk : 4 * akk + r);
+        if (a < m) {
+          double* o = out + (R.out_off + a) * NVP + 16 * wave + arow;
+          if (mode == MODE_STORE) *o = (double)acc[ti][r];
+          else *o += (double)acc[ti][r];
+        }
+      }
+    }
+  }
 }
 
 // Transposed block-column product (op 'T') for the coupling and dense
@@ -513,6 +816,38 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
       else H2_MFMA3(NT, 4, 64);                         \
     }                                                   \
   } while (0)
+  // kc: 32 or 64 columns per chunk; 0: pipelined kernel; 1, 2: balanced
+  // kernel with 32 or 16 columns; 3: balanced, 16 columns, loads issued two
+  // chunks ahead (these take 64 vectors and rows of at most 64 outputs; other
+  // launches fall back to 64 columns)
+  if ((kc == 0 && nvp != 64) || ((kc >= 1 && kc <= 3) && (nvp != 64 || max_rows > 64))) kc = 64;
+  if (kc >= 1 && kc <= 3) {
+#define H2_BAL(KCV, DEEP, MT)                                                                                   \
+  hipLaunchKernelGGL((k_rows_mfma_bal<T, KCV, DEEP, MT>), g, block, 0, s, rows, nrows, colend, in_off, data, in, \
+                     out, mode, remap)
+#define H2_BAL_MT(KCV, DEEP)                       \
+  do {                                             \
+    if (max_rows <= 16) H2_BAL(KCV, DEEP, 1);      \
+    else if (max_rows <= 32) H2_BAL(KCV, DEEP, 2); \
+    else if (max_rows <= 48) H2_BAL(KCV, DEEP, 3); \
+    else H2_BAL(KCV, DEEP, 4);                     \
+  } while (0)
+    if (kc == 1) H2_BAL_MT(32, false);
+    else if (kc == 2) H2_BAL_MT(16, false);
+    else H2_BAL_MT(16, true);
+#undef H2_BAL_MT
+#undef H2_BAL
+    return hipGetLastError();
+  }
+  if (kc == 0) {
+    if (max_rows <= 64)
+      hipLaunchKernelGGL((k_rows_mfma_pipe<T, 1>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, mode,
+                         remap);
+    else
+      hipLaunchKernelGGL((k_rows_mfma_pipe<T, 4>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, mode,
+                         remap);
+    return hipGetLastError();
+  }
   switch (nvp) {
     case 16: H2_MFMA(1); break;
     case 32: H2_MFMA(2); break;
@@ -801,15 +1136,17 @@ hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s
 hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pinv, double* xt, int64_t n, int nv,
                                 int nvp, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute_in_rm, dim3(grid1d(n, 256)), dim3(256), 0, s, X, ldx, pinv, xt, n, nv, nvp);
+  if (nvp > kPassVectorsMfma || nv > nvp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_permute_in_rm, dim3(grid1d(n, kPermTile)), dim3(256), 0, s, X, ldx, pinv, xt, n, nv, nvp);
   return hipGetLastError();
 }
 
 hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double alpha, double beta, double* Y,
                                  int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute_out_rm, dim3(grid1d(n, 256)), dim3(256), 0, s, Z, pinv, alpha, beta, Y, ldy, n, nv,
-                     nvp);
+  if (nvp > kPassVectorsMfma || nv > nvp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_permute_out_rm, dim3(grid1d(n, kPermTile)), dim3(256), 0, s, Z, pinv, alpha, beta, Y, ldy, n,
+                     nv, nvp);
   return hipGetLastError();
 }
 

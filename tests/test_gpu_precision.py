@@ -114,3 +114,29 @@ def test_tune_keeps_results_bitwise(cfg):
         if prec == "fp64":
             assert np.all(np.abs(after - want) <= 1e-12 * B)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_launch_settings_bitwise(prec):
+    """Every fixed setting of the multi-vector launches (chunk width or the
+    pipelined kernel, grid, XCD mapping, row order) gives bitwise the same
+    product at 64 and 40 vectors."""
+    from paper_2109_05451_amd import H2Operator
+    buf = np.array(h2gen.build(h2gen.points(5000, 2, 6), leaf=48, p=6, eta=0.7, kernel="exp").array, copy=True)
+    ref = oracle.Oracle(buf)
+    g = H2Operator(buf)
+    for nv in (64, 40):
+        X = h2gen.vectors(g.n, nv, 13)
+        base = run(g, X, "N", precision=prec)
+        if prec == "fp64":
+            want, B = ref.gemv(X), ref.gemv(X, absval=True)
+            assert np.all(np.abs(base - want) <= 1e-12 * B)
+        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 32, 64)
+        for kc in kcs:
+            for grid in (0, 1024):
+                for xcd in (False, True):
+                    for tree in (0, 1):
+                        g.tune_set(prec, kc, grid, xcd, tree)
+                        got = run(g, X, "N", precision=prec)
+                        assert np.array_equal(got, base), (prec, nv, kc, grid, xcd, tree)
+    g.close()
