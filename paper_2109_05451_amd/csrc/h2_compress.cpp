@@ -544,7 +544,14 @@ int compress_impl(h2_op_s* h, double tau, hipStream_t s, h2_handle* out, h2_comp
   Ctx C;
   C.h = h;
   C.s = s;
-  RC(parse(reinterpret_cast<const uint8_t*>(h->prefix.data()), h->file_len, &C.P));
+  {
+    const int prc = parse(reinterpret_cast<const uint8_t*>(h->prefix.data()), h->file_len, &C.P);
+    if (prc != H2_OK) {
+      set_error("recompression: the operator's stored structure does not parse (" + std::string(h2_last_error()) +
+                ")");
+      return prc;
+    }
+  }
   const Parsed& P = C.P;
   const int64_t q = P.q;
   const bool sep = (P.flags & 1u) != 0;
@@ -714,7 +721,17 @@ int compress_impl(h2_op_s* h, double tau, hipStream_t s, h2_handle* out, h2_comp
                                                           (P.off_D - P.off_U));
   h2_handle nh = nullptr;
   const int rc = load_handle(hbp, total, h->device, d_dense, &nh);
-  if (rc != H2_OK) return rc;
+  if (rc != H2_OK) {
+    std::string msg = "recompression: the new representation does not load (" + std::string(h2_last_error()) +
+                      "); ranks";
+    for (int64_t l = 0; l <= q; ++l) msg += " " + std::to_string(kr[l]) + "/" + std::to_string(kc[l]);
+    msg += "; level_ptr";
+    for (int64_t l = 0; l <= q + 1 && l < 6; ++l) msg += " " + std::to_string(reinterpret_cast<const int64_t*>(hbp + 128)[l]);
+    msg += "; sizes U " + std::to_string(nw.U) + " E " + std::to_string(nw.E) + " S " + std::to_string(nw.S) +
+           " total " + std::to_string(total) + " prefix " + std::to_string(pre);
+    set_error(msg);
+    return rc;
+  }
   CK(hipEventRecord(ev[5], nullptr), "hipEventRecord");
   CK(hipEventSynchronize(ev[5]), "hipEventSynchronize");
   if (info) {
