@@ -213,9 +213,9 @@ int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
 /* Set the multi-vector launch parameters that h2_tune would pick, the same
  * for every launch of precision `prec`: kc = 32 or 64 columns per chunk, 0
  * for the software-pipelined kernel, 1 or 2 for the balanced kernel with 32
- * or 16 columns, 3 for the balanced kernel with 16 columns and loads issued
- * two chunks ahead (0-3 take passes of 64 vectors, 1-3 rows of at most 64
- * outputs; other launches use 64 columns); grid = workgroups (0 = one per
+ * or 16 columns, 3 or 4 for the balanced kernel with 16 or 32 columns and
+ * loads issued two chunks ahead (0-4 take passes of 64 vectors, 1-4 rows of
+ * at most 64 outputs; other launches use 64 columns); grid = workgroups (0 = one per
  * row); xcd != 0 for XCD-aware row ranges; tree_order != 0 for tree-ordered
  * coupling and dense rows.  Results do not change (same summation order).  For
  * reproducible timing and for tests.  Errors: H2_EINVAL. */

@@ -356,6 +356,94 @@ int read_counts(Ctx& C, const Tree& X, int64_t l, int64_t* kmax) {
   return H2_OK;
 }
 
+// ---- step 3, one level of parents (level l-1) when every stacked rank
+// n_p = children * k'_l is at most 64: the left singular vectors of
+// M = N_p R_p^T are the eigenvectors of M M^T = N_p G_p N_p^T (order n_p)
+int truncate_level_direct(Ctx& C, Tree& X, int64_t l, double thr2) {
+  const Parsed& P = C.P;
+  const int64_t kl = X.k[l], kp = X.k[l - 1], kln = X.knew[l];
+  const int64_t b0 = P.level_ptr[l - 1], b1 = P.level_ptr[l];
+  // per parent: n_p x n_p Gram matrix and eigenvectors, n_p eigenvalues
+  std::vector<int64_t> off(b1 - b0 + 1, 0);
+  for (int64_t p = b0; p < b1; ++p) {
+    const int64_t np = (int64_t)C.kids[p].size() * kln;
+    off[p - b0 + 1] = off[p - b0] + np * np;
+  }
+  double *Dg = nullptr, *Dz = nullptr, *Dl = nullptr;
+  RC(C.ar.alloc(&Dg, off.back(), C.s));
+  RC(C.ar.alloc(&Dz, off.back(), C.s));
+  RC(C.ar.alloc(&Dl, (b1 - b0) * kMaxCompressRank, C.s));
+  std::vector<GemmTask> g1;
+  std::vector<GemmPair> p1;
+  std::vector<TripleTask> tt;
+  std::vector<EigTask> et;
+  std::vector<CountTask> cnt;
+  std::vector<ScaleTask> sc;
+  for (int64_t p = b0; p < b1; ++p) {
+    const auto& ch = C.kids[p];
+    const int64_t np = (int64_t)ch.size() * kln, ldn = std::max<int64_t>(np, 1);
+    if (np == 0) continue;
+    double* N = X.stack + C.stoff[p];
+    // N_p = [T_c E_c] (np x kp)
+    for (size_t i = 0; i < ch.size() && kl > 0; ++i) {
+      const int64_t c = ch[i];
+      RC(add_gemm(C, g1, N + i * kln, ldn, (int)kln, (int)kp, 0.0,
+                  {GemmPair{X.Tt + C.nk2[c], transfer(C, X, X.To, c), kln, kl, (int32_t)kl, 0}}, p1));
+    }
+    // N_p G_p N_p^T
+    TripleTask t{};
+    t.L = N; t.ldl = ldn;
+    t.M = X.G + C.nk2[p]; t.ldm = kp;
+    t.R = N; t.ldr = ldn;
+    t.C = Dg + off[p - b0]; t.ldc = np;
+    t.a = (int32_t)np; t.k1 = (int32_t)kp; t.k2 = (int32_t)kp; t.b = (int32_t)np;
+    t.beta = 0.0;
+    RC(add_triple(C, tt, t));
+    double* lam = Dl + (p - b0) * kMaxCompressRank;
+    RC(add_eig(C, et, Dg + off[p - b0], np, lam, Dz + off[p - b0], np, (int)np));
+    // N G N^T has rank at most kp: only its kp leading eigenvalues can be kept
+    cnt.push_back(CountTask{lam, (int32_t)std::min(np, kp), (int32_t)p});
+    sc.push_back(ScaleTask{Dz + off[p - b0], np, lam, (int32_t)np, (int32_t)np, (int32_t)p, 0});
+  }
+  RC(launch_gemm_tasks(C, g1, p1));
+  RC(launch_tasks(C, tt, launch_triple));
+  RC(launch_eigs(C, et));
+  if (!cnt.empty()) {
+    CountTask* d = nullptr;
+    RC(C.ar.upload(cnt, &d, C.s));
+    CK(launch_count(d, (int64_t)cnt.size(), thr2, X.counts, C.s), "count");
+  }
+  RC(read_counts(C, X, l - 1, &X.knew[l - 1]));
+  const int64_t kpn = X.knew[l - 1];
+  if (!sc.empty()) {
+    ScaleTask* d = nullptr;
+    RC(C.ar.upload(sc, &d, C.s));
+    CK(launch_scale_cols(d, (int64_t)sc.size(), X.counts, 0, C.s), "scale");
+  }
+  if (kpn == 0) return H2_OK;
+  // E'_c = rows of child c of W[:, :kpn]; T_p = W[:, :kpn]^T N_p (kpn x kp).
+  // W has only n_p columns: where n_p < kpn the rest of E'_c and of T_p are
+  // the zero padding the arena starts with.
+  std::vector<CopyTask> ct;
+  std::vector<GemmTask> g2;
+  std::vector<GemmPair> p2;
+  for (int64_t p = b0; p < b1; ++p) {
+    const auto& ch = C.kids[p];
+    const int64_t np = (int64_t)ch.size() * kln, ldn = std::max<int64_t>(np, 1);
+    if (np == 0) continue;
+    const int64_t kw = std::min(kpn, np);
+    const double* W = Dz + off[p - b0];
+    for (size_t i = 0; i < ch.size(); ++i)
+      RC(add_copy(C, ct, W + i * kln, np, const_cast<double*>(transfer(C, X, X.Et, ch[i])), kln, (int)kln, (int)kw,
+                  false));
+    RC(add_gemm(C, g2, X.Tt + C.nk2[p], kpn, (int)kw, (int)kp, 0.0,
+                {GemmPair{W, X.stack + C.stoff[p], np, ldn, (int32_t)np, 1}}, p2));
+  }
+  RC(launch_tasks(C, ct, launch_copy));
+  RC(launch_gemm_tasks(C, g2, p2));
+  return H2_OK;
+}
+
 // ---- step 3: truncation upsweep of one tree
 int truncate(Ctx& C, Tree& X, double tau) {
   const Parsed& P = C.P;
@@ -425,6 +513,13 @@ int truncate(Ctx& C, Tree& X, double tau) {
   // inner levels, parents on level l-1
   for (int64_t l = q; l >= 1; --l) {
     const int64_t kl = X.k[l], kp = X.k[l - 1], kln = X.knew[l];
+    int64_t npmax = 0;
+    for (int64_t p = P.level_ptr[l - 1]; p < P.level_ptr[l]; ++p)
+      npmax = std::max<int64_t>(npmax, (int64_t)C.kids[p].size() * kln);
+    if (kp > 0 && npmax <= kMaxCompressRank) {
+      RC(truncate_level_direct(C, X, l, thr2));
+      continue;
+    }
     std::vector<GemmTask> g1, g2, g3;
     std::vector<GemmPair> p1, p2, p3;
     std::vector<EigTask> e1, e2;

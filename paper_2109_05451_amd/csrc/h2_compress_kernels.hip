@@ -247,51 +247,40 @@ __global__ __launch_bounds__(kCT) void k_triple(const TripleTask* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi for symmetric n x n matrices (n <= N), one
-// wavefront per matrix (W wavefronts, so W matrices, per workgroup; the
-// matrix and its eigenvectors live in LDS and only lanes of one wavefront
-// touch them, so phases are ordered by wavefront-scope fences).  Each round
-// applies n'/2 disjoint rotations (n' = n rounded up to even; the padding
-// index only meets identity rotations) in tournament order, n' - 1 rounds
-// per sweep, until a sweep rotates nothing.  Rotation (c, s) from the 2 x 2
-// symmetric Schur decomposition zeroes A[p][q] in J^T A J, J = [[c, s], [-s, c]].
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-template <int N, int W>
-__global__ __launch_bounds__(64 * W) void k_eig(const EigTask* __restrict__ tasks, int64_t ntasks) {
+// Parallel cyclic Jacobi for a symmetric n x n matrix (n <= N), one
+// workgroup per matrix, matrix and eigenvectors in LDS (sized by N, so small
+// orders leave room for more workgroups per CU): rounds of n'/2 disjoint
+// rotations (n' = n rounded up to even; the padding index only meets
+// identity rotations), tournament ordering, n' - 1 rounds per sweep, until a
+// sweep rotates nothing.  Rotation (c, s) from the 2 x 2 symmetric Schur
+// decomposition zeroes A[p][q] in J^T A J, J = [[c, s], [-s, c]].
+template <int N>
+__global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) {
   constexpr int LD = N + 1;
-  __shared__ double sA_all[W][N * LD];
-  __shared__ double sV_all[W][N * LD];
-  __shared__ double rc_all[W][N / 2], rs_all[W][N / 2];
-  __shared__ int rp_all[W][N / 2], rq_all[W][N / 2];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t ti = (int64_t)blockIdx.x * W + wv;
-  if (ti >= ntasks) return;  // whole wavefront leaves; no workgroup barrier below
-  double* sA = sA_all[wv];
-  double* sV = sV_all[wv];
-  double* rc = rc_all[wv];
-  double* rs = rs_all[wv];
-  int* rp = rp_all[wv];
-  int* rq = rq_all[wv];
-  const EigTask T = tasks[ti];
-  const int n = T.n;
+  __shared__ double sA[N * LD];
+  __shared__ double sV[N * LD];
+  __shared__ double rc[N / 2], rs[N / 2];
+  __shared__ int rp[N / 2], rq[N / 2];
+  __shared__ int s_rot;
+  __shared__ double s_lam[N];
+  const EigTask T = tasks[blockIdx.x];
+  const int n = T.n, tid = threadIdx.x;
   const int np = (n + 1) & ~1, half = np / 2;
-  for (int e = lane; e < n * n; e += 64) {
+  for (int e = tid; e < n * n; e += kCT) {
     const int j = e / n, i = e - j * n;
+    // symmetrize (the inputs are symmetric up to rounding)
     sA[i * LD + j] = 0.5 * (T.G[i + (int64_t)j * T.ldg] + T.G[j + (int64_t)i * T.ldg]);
     sV[i * LD + j] = i == j ? 1.0 : 0.0;
   }
-  wave_sync();
+  __syncthreads();
   for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
-    bool rot = false;
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
-      for (int k = lane; k < half; k += 64) {
+      if (tid < half) {
         int p, q;
-        if (k == 0) { p = round; q = np - 1; }
-        else { p = (round + k) % (np - 1); q = (round - k + (np - 1)) % (np - 1); }
+        if (tid == 0) { p = round; q = np - 1; }
+        else { p = (round + tid) % (np - 1); q = (round - tid + (np - 1)) % (np - 1); }
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
@@ -301,13 +290,14 @@ __global__ __launch_bounds__(64 * W) void k_eig(const EigTask* __restrict__ task
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
-            rot = true;
+            s_rot = 1;
           }
         }
-        rp[k] = p; rq[k] = q; rc[k] = c; rs[k] = s;
+        rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s;
       }
-      wave_sync();
-      for (int e = lane; e < half * n; e += 64) {
+      __syncthreads();
+      // rows: p' = c p - s q, q' = s p + c q
+      for (int e = tid; e < half * n; e += kCT) {
         const int k = e / n, j = e - k * n;
         const int p = rp[k], q = rq[k];
         if (q < n && rs[k] != 0.0) {
@@ -317,8 +307,9 @@ __global__ __launch_bounds__(64 * W) void k_eig(const EigTask* __restrict__ task
           sA[q * LD + j] = s * ap + c * aq;
         }
       }
-      wave_sync();
-      for (int e = lane; e < half * n; e += 64) {
+      __syncthreads();
+      // columns of A and V: p'' = c p - s q, q'' = s p + c q
+      for (int e = tid; e < half * n; e += kCT) {
         const int k = e / n, i = e - k * n;
         const int p = rp[k], q = rq[k];
         if (q < n && rs[k] != 0.0) {
@@ -331,18 +322,18 @@ __global__ __launch_bounds__(64 * W) void k_eig(const EigTask* __restrict__ task
           sV[i * LD + q] = s * vp + c * vq;
         }
       }
-      wave_sync();
+      __syncthreads();
     }
-    if (!__any(rot)) break;
+    if (s_rot == 0) break;
+    __syncthreads();
   }
   // descending order (ties by index)
-  for (int i = lane; i < n; i += 64) {
-    const double li = sA[i * LD + i];
+  for (int i = tid; i < n; i += kCT) s_lam[i] = sA[i * LD + i];
+  __syncthreads();
+  for (int i = tid; i < n; i += kCT) {
+    const double li = s_lam[i];
     int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = sA[j * LD + j];
-      rank += (lj > li) || (lj == li && j < i);
-    }
+    for (int j = 0; j < n; ++j) rank += (s_lam[j] > li) || (s_lam[j] == li && j < i);
     T.lam[rank] = li;
     for (int row = 0; row < n; ++row) T.Z[row + (int64_t)rank * T.ldz] = sV[row * LD + i];
   }
@@ -453,14 +444,10 @@ hipError_t launch_triple(const TripleTask* t, int64_t n, hipStream_t s) {
 }
 hipError_t launch_eig(const EigTask* t, int64_t n, int nmax, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (nmax <= 32)
-    hipLaunchKernelGGL((k_eig<32, 4>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, n);
-  else if (nmax <= 48)
-    hipLaunchKernelGGL((k_eig<48, 4>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, t, n);
-  else if (nmax <= kMaxCompressRank)
-    hipLaunchKernelGGL((k_eig<64, 2>), dim3((unsigned)((n + 1) / 2)), dim3(128), 0, s, t, n);
-  else
-    return hipErrorInvalidValue;
+  if (nmax <= 32) hipLaunchKernelGGL((k_eig<32>), grid_of(n), dim3(kCT), 0, s, t);
+  else if (nmax <= 48) hipLaunchKernelGGL((k_eig<48>), grid_of(n), dim3(kCT), 0, s, t);
+  else if (nmax <= kMaxCompressRank) hipLaunchKernelGGL((k_eig<64>), grid_of(n), dim3(kCT), 0, s, t);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 hipError_t launch_mask_gram(const MaskTask* t, int64_t n, hipStream_t s) {

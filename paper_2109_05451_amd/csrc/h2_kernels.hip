@@ -817,11 +817,11 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
     }                                                   \
   } while (0)
   // kc: 32 or 64 columns per chunk; 0: pipelined kernel; 1, 2: balanced
-  // kernel with 32 or 16 columns; 3: balanced, 16 columns, loads issued two
-  // chunks ahead (these take 64 vectors and rows of at most 64 outputs; other
-  // launches fall back to 64 columns)
-  if ((kc == 0 && nvp != 64) || ((kc >= 1 && kc <= 3) && (nvp != 64 || max_rows > 64))) kc = 64;
-  if (kc >= 1 && kc <= 3) {
+  // kernel with 32 or 16 columns; 3, 4: balanced, 16 or 32 columns, loads
+  // issued two chunks ahead (these take 64 vectors and rows of at most 64
+  // outputs; other launches fall back to 64 columns)
+  if ((kc == 0 && nvp != 64) || ((kc >= 1 && kc <= 4) && (nvp != 64 || max_rows > 64))) kc = 64;
+  if (kc >= 1 && kc <= 4) {
 #define H2_BAL(KCV, DEEP, MT)                                                                                   \
   hipLaunchKernelGGL((k_rows_mfma_bal<T, KCV, DEEP, MT>), g, block, 0, s, rows, nrows, colend, in_off, data, in, \
                      out, mode, remap)
@@ -834,7 +834,8 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
   } while (0)
     if (kc == 1) H2_BAL_MT(32, false);
     else if (kc == 2) H2_BAL_MT(16, false);
-    else H2_BAL_MT(16, true);
+    else if (kc == 3) H2_BAL_MT(16, true);
+    else H2_BAL_MT(32, true);
 #undef H2_BAL_MT
 #undef H2_BAL
     return hipGetLastError();
