@@ -214,8 +214,11 @@ int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
  * for every launch of precision `prec`: kc = 32 or 64 columns per chunk, 0
  * for the software-pipelined kernel, 1 or 2 for the balanced kernel with 32
  * or 16 columns, 3 or 4 for the balanced kernel with 16 or 32 columns and
- * loads issued two chunks ahead (0-4 take passes of 64 vectors, 1-4 rows of
- * at most 64 outputs; other launches use 64 columns); grid = workgroups (0 = one per
+ * loads issued two chunks ahead, 5 or 6 for the balanced kernel with 16
+ * columns (loads one or two chunks ahead) compiled for four workgroups per
+ * CU, 7 or 8 the same with 8 columns and five workgroups per CU (0-8 take
+ * passes of 64 vectors, 1-8 rows of at most 64 outputs; other launches use
+ * 64 columns); grid = workgroups (0 = one per
  * row); xcd != 0 for XCD-aware row ranges; tree_order != 0 for tree-ordered
  * coupling and dense rows.  Results do not change (same summation order).  For
  * reproducible timing and for tests.  Errors: H2_EINVAL. */

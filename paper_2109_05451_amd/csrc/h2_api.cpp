@@ -757,15 +757,15 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   // best candidate of one launch; its time (ms, two timed runs) in *tbest
   auto tune_one = [&](Launch& L, int mode_override, float* tbest) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
-    const int kcs[7] = {32, 64, 0, 1, 2, 3, 4};  // 0: pipelined, 1-4: balanced (64 vectors only)
+    const int kcs[11] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8};  // 0: pipelined, 1-8: balanced (64 vectors only)
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
     int best_kc = L.kcp[pi], best_remap = L.remapp[pi];
     int64_t best_grid = L.gridp[pi];
     for (int kc : kcs) {
       if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
-      if (kc >= 0 && kc <= 4 && nvp != 64) continue;
-      if (kc >= 1 && kc <= 4 && L.max_rows > 64) continue;
+      if (kc >= 0 && kc <= 8 && nvp != 64) continue;
+      if (kc >= 1 && kc <= 8 && L.max_rows > 64) continue;
       for (int64_t g : grids)
         for (int remap = 0; remap < 2; ++remap) {
           if (g != 0 && g >= L.row_count) continue;
@@ -838,8 +838,8 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
     set_error("unknown precision");
     return H2_EINVAL;
   }
-  if (!(kc >= 0 && kc <= 4) && kc != 32 && kc != 64) {
-    set_error("kc must be 0-4, 32 or 64");
+  if (!(kc >= 0 && kc <= 8) && kc != 32 && kc != 64) {
+    set_error("kc must be 0-8, 32 or 64");
     return H2_EINVAL;
   }
   if (prec == H2_PREC_BF16 && kc != 64) { set_error("the BF16 kernel has kc 64 only"); return H2_EINVAL; }

@@ -531,9 +531,12 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_pipe(const RowDesc* __restrict
 // chunk of KC columns go through LDS, double-buffered: the matrix chunk is a
 // contiguous m x KC slice (coalesced loads), the gathered input chunk is
 // KC x 64; the next chunk is loaded into registers before the current
-// chunk's MFMAs and stored after them, with one barrier per chunk.
-template <typename T, int KC, bool DEEP, int MT>
-__global__ __launch_bounds__(kT) void k_rows_mfma_bal(const RowDesc* __restrict__ rows, int64_t nrows,
+// chunk's MFMAs and stored after them, with one barrier per chunk.  OCC > 1
+// asks the compiler for registers enough for OCC workgroups per CU (four fit
+// the 16-column chunk's LDS, more the 8-column one's), trading a little
+// spilling for latency hiding.
+template <typename T, int KC, bool DEEP, int MT, int OCC>
+__global__ __launch_bounds__(kT, OCC) void k_rows_mfma_bal(const RowDesc* __restrict__ rows, int64_t nrows,
                                                       const int32_t* __restrict__ colend,
                                                       const int64_t* __restrict__ in_off,
                                                       const T* __restrict__ data, const double* in, double* out,
@@ -818,24 +821,30 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
   } while (0)
   // kc: 32 or 64 columns per chunk; 0: pipelined kernel; 1, 2: balanced
   // kernel with 32 or 16 columns; 3, 4: balanced, 16 or 32 columns, loads
-  // issued two chunks ahead (these take 64 vectors and rows of at most 64
-  // outputs; other launches fall back to 64 columns)
-  if ((kc == 0 && nvp != 64) || ((kc >= 1 && kc <= 4) && (nvp != 64 || max_rows > 64))) kc = 64;
-  if (kc >= 1 && kc <= 4) {
-#define H2_BAL(KCV, DEEP, MT)                                                                                   \
-  hipLaunchKernelGGL((k_rows_mfma_bal<T, KCV, DEEP, MT>), g, block, 0, s, rows, nrows, colend, in_off, data, in, \
-                     out, mode, remap)
-#define H2_BAL_MT(KCV, DEEP)                       \
-  do {                                             \
-    if (max_rows <= 16) H2_BAL(KCV, DEEP, 1);      \
-    else if (max_rows <= 32) H2_BAL(KCV, DEEP, 2); \
-    else if (max_rows <= 48) H2_BAL(KCV, DEEP, 3); \
-    else H2_BAL(KCV, DEEP, 4);                     \
+  // issued two chunks ahead; 5, 6: balanced, 16 columns (loads one or two
+  // chunks ahead) with registers for four workgroups per CU; 7, 8: the same
+  // with 8 columns and five workgroups per CU (0-8 take 64 vectors, 1-8 rows
+  // of at most 64 outputs; other launches fall back to 64 columns)
+  if ((kc == 0 && nvp != 64) || ((kc >= 1 && kc <= 8) && (nvp != 64 || max_rows > 64))) kc = 64;
+  if (kc >= 1 && kc <= 8) {
+#define H2_BAL(KCV, DEEP, MT, OCC)                                                                      \
+  hipLaunchKernelGGL((k_rows_mfma_bal<T, KCV, DEEP, MT, OCC>), g, block, 0, s, rows, nrows, colend, in_off, \
+                     data, in, out, mode, remap)
+#define H2_BAL_MT(KCV, DEEP, OCC)                       \
+  do {                                                  \
+    if (max_rows <= 16) H2_BAL(KCV, DEEP, 1, OCC);      \
+    else if (max_rows <= 32) H2_BAL(KCV, DEEP, 2, OCC); \
+    else if (max_rows <= 48) H2_BAL(KCV, DEEP, 3, OCC); \
+    else H2_BAL(KCV, DEEP, 4, OCC);                     \
   } while (0)
-    if (kc == 1) H2_BAL_MT(32, false);
-    else if (kc == 2) H2_BAL_MT(16, false);
-    else if (kc == 3) H2_BAL_MT(16, true);
-    else H2_BAL_MT(32, true);
+    if (kc == 1) H2_BAL_MT(32, false, 1);
+    else if (kc == 2) H2_BAL_MT(16, false, 1);
+    else if (kc == 3) H2_BAL_MT(16, true, 1);
+    else if (kc == 4) H2_BAL_MT(32, true, 1);
+    else if (kc == 5) H2_BAL_MT(16, false, 4);
+    else if (kc == 6) H2_BAL_MT(16, true, 4);
+    else if (kc == 7) H2_BAL_MT(8, false, 5);
+    else H2_BAL_MT(8, true, 5);
 #undef H2_BAL_MT
 #undef H2_BAL
     return hipGetLastError();

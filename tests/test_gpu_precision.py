@@ -131,7 +131,7 @@ def test_launch_settings_bitwise(prec):
         if prec == "fp64":
             want, B = ref.gemv(X), ref.gemv(X, absval=True)
             assert np.all(np.abs(base - want) <= 1e-12 * B)
-        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 4, 32, 64)
+        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 4, 5, 6, 7, 8, 32, 64)
         for kc in kcs:
             for grid in (0, 1024):
                 for xcd in (False, True):
