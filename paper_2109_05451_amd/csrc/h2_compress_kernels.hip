@@ -263,16 +263,30 @@ __global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) 
   __shared__ int rp[N / 2], rq[N / 2];
   __shared__ int s_rot;
   __shared__ double s_lam[N];
+  __shared__ double s_red[kCT];
   const EigTask T = tasks[blockIdx.x];
   const int n = T.n, tid = threadIdx.x;
   const int np = (n + 1) & ~1, half = np / 2;
+  double sq = 0.0;
   for (int e = tid; e < n * n; e += kCT) {
     const int j = e / n, i = e - j * n;
     // symmetrize (the inputs are symmetric up to rounding)
-    sA[i * LD + j] = 0.5 * (T.G[i + (int64_t)j * T.ldg] + T.G[j + (int64_t)i * T.ldg]);
+    const double a = 0.5 * (T.G[i + (int64_t)j * T.ldg] + T.G[j + (int64_t)i * T.ldg]);
+    sA[i * LD + j] = a;
     sV[i * LD + j] = i == j ? 1.0 : 0.0;
+    sq += a * a;
   }
+  s_red[tid] = sq;
   __syncthreads();
+  for (int w = kCT / 2; w > 0; w >>= 1) {
+    if (tid < w) s_red[tid] += s_red[tid + w];
+    __syncthreads();
+  }
+  // off-diagonal entries below 1e-16 of the Frobenius norm are not rotated:
+  // besides the relative test, this stops the sweeps once only rounding
+  // noise among the (many) negligible eigenvalues is left, at an absolute
+  // accuracy far below any threshold the truncation applies
+  const double floor_abs = 1e-16 * sqrt(s_red[0]);
   for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(kCT) void k_eig(const EigTask* __restrict__ tasks) 
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double app = sA[p * LD + p], aqq = sA[q * LD + q], apq = sA[p * LD + q];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+          if (fabs(apq) > 1e-300 && fabs(apq) > floor_abs && fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
