@@ -60,13 +60,28 @@ void append_gather(GatherTables& t, const RowSpec& r) {
   t.rows.push_back(R);
 }
 
-// Append a phase of streaming rows (narrow rows to the tabled kernel, wide
-// ones to the fallback), longest rows first for load balance.
-void add_stream_phase(h2_op_s* h, std::vector<RowSpec>& rows, int arr, int in, int out, int mode, bool sort,
-                      std::vector<Launch>& dst) {
-  if (sort)
-    std::stable_sort(rows.begin(), rows.end(),
-                     [](const RowSpec& a, const RowSpec& b) { return row_work(a) > row_work(b); });
+// Row indices, most work (columns x outputs) first; ties keep their order.
+std::vector<size_t> order_by_work(const std::vector<RowSpec>& rows) {
+  std::vector<int64_t> w(rows.size());
+  for (size_t i = 0; i < rows.size(); ++i) w[i] = row_work(rows[i]);
+  std::vector<size_t> o(rows.size());
+  std::iota(o.begin(), o.end(), 0);
+  std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) { return w[a] > w[b]; });
+  return o;
+}
+
+// Row indices in output position order (tree order).
+std::vector<size_t> order_by_position(const std::vector<RowSpec>& rows) {
+  std::vector<size_t> o(rows.size());
+  std::iota(o.begin(), o.end(), 0);
+  std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) { return rows[a].out_off < rows[b].out_off; });
+  return o;
+}
+
+// Append a phase of streaming rows taken in the given order (narrow rows to
+// the tabled kernel, wide ones to the fallback).
+void add_stream_rows(h2_op_s* h, const std::vector<RowSpec>& rows, const size_t* order, size_t count, int arr,
+                     int in, int out, int mode, std::vector<Launch>& dst) {
   Launch narrow, wide;
   narrow.kind = KIND_STREAM; wide.kind = KIND_WIDE;
   narrow.arr = wide.arr = arr;
@@ -75,7 +90,8 @@ void add_stream_phase(h2_op_s* h, std::vector<RowSpec>& rows, int arr, int in, i
   narrow.mode = wide.mode = mode;
   narrow.row_begin = (int64_t)h->rt.rows.size();
   wide.row_begin = (int64_t)h->wide.rows.size();
-  for (const RowSpec& r : rows) {
+  for (size_t i = 0; i < count; ++i) {
+    const RowSpec& r = rows[order ? order[i] : i];
     if ((int64_t)r.blks.size() <= kNbMax) {
       append_row(h->rt, r);
       narrow.max_rows = std::max(narrow.max_rows, r.nrows);
@@ -90,7 +106,21 @@ void add_stream_phase(h2_op_s* h, std::vector<RowSpec>& rows, int arr, int in, i
   if (wide.row_count) dst.push_back(wide);
 }
 
-void add_gather_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int in, int out, std::vector<Launch>& dst) {
+// A phase of streaming rows in emission order, or longest rows first for
+// load balance.
+void add_stream_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int arr, int in, int out, int mode, bool sort,
+                      std::vector<Launch>& dst) {
+  if (!sort) {
+    add_stream_rows(h, rows, nullptr, rows.size(), arr, in, out, mode, dst);
+    return;
+  }
+  const std::vector<size_t> o = order_by_work(rows);
+  add_stream_rows(h, rows, o.data(), o.size(), arr, in, out, mode, dst);
+}
+
+// Rows first, first + step, ... of `rows` as one launch of the transposed kernel.
+void add_gather_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int in, int out, std::vector<Launch>& dst,
+                      size_t first = 0, size_t step = 1) {
   Launch L;
   L.kind = KIND_GATHER;
   L.arr = ARR_MAT;
@@ -98,7 +128,7 @@ void add_gather_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int in, int 
   L.out = out;
   L.mode = MODE_STORE;
   L.row_begin = (int64_t)h->gt.rows.size();
-  for (const RowSpec& r : rows) append_gather(h->gt, r);
+  for (size_t i = first; i < rows.size(); i += step) append_gather(h->gt, rows[i]);
   L.row_count = (int64_t)h->gt.rows.size() - L.row_begin;
   if (L.row_count) dst.push_back(L);
 }
@@ -166,28 +196,25 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
     for (int64_t hh = 1; hh <= q; ++hh) add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
     add_stream_phase(h, R.couple, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple);
     {
-      auto by_pos = [](const RowSpec& a, const RowSpec& b) { return a.out_off < b.out_off; };
-      std::vector<RowSpec> loc = R.couple;
-      std::stable_sort(loc.begin(), loc.end(), by_pos);
-      add_stream_phase(h, loc, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, false, plan.couple_loc);
-      loc = R.dense;
-      std::stable_sort(loc.begin(), loc.end(), by_pos);
-      const size_t half = loc.size() / 2;
-      std::vector<RowSpec> h1(loc.begin(), loc.begin() + half), h2(loc.begin() + half, loc.end());
-      add_stream_phase(h, h1, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense_loc);
-      add_stream_phase(h, h2, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense2_loc);
+      // the same rows in tree order; the dense rows in two halves of the domain
+      const std::vector<size_t> oc = order_by_position(R.couple);
+      add_stream_rows(h, R.couple, oc.data(), oc.size(), ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, plan.couple_loc);
+      const std::vector<size_t> od = order_by_position(R.dense);
+      const size_t half = od.size() / 2;
+      add_stream_rows(h, R.dense, od.data(), half, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, plan.dense_loc);
+      add_stream_rows(h, R.dense, od.data() + half, od.size() - half, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE,
+                      plan.dense2_loc);
       for (auto* v : {&plan.dense_loc, &plan.dense2_loc})
         for (Launch& L : *v) L.lowrank = false;
     }
     for (int64_t l = 1; l <= q; ++l) add_stream_phase(h, R.down[l - 1], ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
     {
       // two halves with the same mix of long and short rows (longest first in each)
-      std::stable_sort(R.dense.begin(), R.dense.end(),
-                       [](const RowSpec& a, const RowSpec& b) { return row_work(a) > row_work(b); });
-      std::vector<RowSpec> h1, h2;
-      for (size_t i = 0; i < R.dense.size(); ++i) (i % 2 ? h2 : h1).push_back(R.dense[i]);
-      add_stream_phase(h, h1, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense);
-      add_stream_phase(h, h2, ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, false, plan.dense2);
+      const std::vector<size_t> o = order_by_work(R.dense);
+      std::vector<size_t> o1, o2;
+      for (size_t i = 0; i < o.size(); ++i) (i % 2 ? o2 : o1).push_back(o[i]);
+      add_stream_rows(h, R.dense, o1.data(), o1.size(), ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, plan.dense);
+      add_stream_rows(h, R.dense, o2.data(), o2.size(), ARR_MAT, BUF_XT, BUF_ZN, MODE_STORE, plan.dense2);
       for (Launch& L : plan.dense) L.lowrank = false;
       for (Launch& L : plan.dense2) L.lowrank = false;
     }
@@ -215,7 +242,7 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
       for (int64_t p = lp[l - 1]; p < lp[l]; ++p) {
         RowSpec r{tET + lay.eoff(lay.cbeg[p], l), hoff[p], H, H, (int32_t)kc[l - 1], {}};
         for (int64_t c = lay.cbeg[p]; c < lay.cbeg[p + 1]; ++c) r.blks.push_back({0, hoff[c], (int32_t)kc[l], 0});
-        rows.push_back(r);
+        rows.push_back(std::move(r));
       }
       add_stream_phase(h, rows, ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
     }
@@ -245,12 +272,8 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
         by_col[P.d_col[b]].push_back({oD + P.ddat[b], P.lo[P.leaf0 + t], 0, msz(P.leaf0 + t)});
     for (int64_t s = 0; s < P.nleaves; ++s)
       rows.push_back({0, P.lo[P.leaf0 + s], n, n, msz(P.leaf0 + s), std::move(by_col[s])});
-    {
-      std::vector<RowSpec> h1, h2;
-      for (size_t i = 0; i < rows.size(); ++i) (i % 2 ? h2 : h1).push_back(rows[i]);
-      add_gather_phase(h, h1, BUF_XT, BUF_ZN, plan.dense);
-      add_gather_phase(h, h2, BUF_XT, BUF_ZN, plan.dense2);
-    }
+    add_gather_phase(h, rows, BUF_XT, BUF_ZN, plan.dense, 0, 2);
+    add_gather_phase(h, rows, BUF_XT, BUF_ZN, plan.dense2, 1, 2);
     for (Launch& L : plan.dense) L.lowrank = false;
     for (Launch& L : plan.dense2) L.lowrank = false;
     rows.clear();
