@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, datasheet
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector and matrix, datasheet
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector and matrix, datasheet
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, datasheet (no sparsity)
 
 
 def measured_traffic(config: str, nv: int, phase: str):
@@ -66,6 +68,33 @@ def algorithmic(st: dict, nv: int, beta_nonzero: bool = False) -> dict:
     }
     return {"flops": flops, "bytes": mat_bytes + vec_bytes, "phase_bytes": phase,
             "phase_flops": {"coupling": 2.0 * nv * ent["S"], "dense": 2.0 * nv * ent["D"]}}
+
+
+def path_roofline(st: dict, nv: int, precision: str, t_ms: float) -> dict:
+    """Roofline time of the whole product at a precision: the low-rank data
+    (U, V, E, F, S) in that precision's bytes and peak, the dense near field
+    and every vector in FP64; T_roof = max(bytes / HBM, sum over the two parts
+    of flops / peak).  frac = T_roof / measured time."""
+    eb = {"fp64": 8.0, "fp32": 4.0, "bf16": 2.0}[precision]
+    peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[precision]
+    lowrank = sum(st["entries_" + k] for k in "UVEFS")
+    dense = st["entries_D"]
+    n = st["n"]
+    vec = 8.0 * n * nv * 2 + 2 * 2 * 8.0 * nv * st["tree_rows"]
+    bytes_ = eb * lowrank + 8.0 * dense + vec
+    t_bytes = bytes_ / (HBM_PEAK_GBS * 1e9)
+    t_flops = 2.0 * nv * lowrank / (peak * 1e12) + 2.0 * nv * dense / (FP64_PEAK_TFLOPS * 1e12)
+    t_roof = max(t_bytes, t_flops)
+    return {"t_roof_ms": round(t_roof * 1e3, 4), "bound": "hbm" if t_bytes >= t_flops else "flops",
+            "frac": round(t_roof * 1e3 / t_ms, 4)}
+
+
+def launches_per_product(g) -> int:
+    """Kernel launches of one single-vector product: the plan's upsweep,
+    coupling, downsweep and dense launches, the leaf expansion and the input
+    permutation."""
+    names = ("up ", "couple ", "down ", "dense1 ", "dense2 ", "out ")
+    return 1 + sum(1 for line in g.plan_info().splitlines() if line.startswith(names))
 
 
 def time_gpu(g, X, Y, nv, steps, warmup, torch, precision="fp64"):
@@ -516,13 +545,16 @@ def main():
                    "csp": st["csp"]},
         "roofline": roofline,
         "path": {"gb_per_s": round(path_gbs, 1), "hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                 "roofline": path_roofline(st, nv, "fp64", r["t_ms"]),
                  "alg_bytes": alg["bytes"], "alg_flops": alg["flops"], "phases_ms": r["prof"]},
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4),
-                       "samples": int(r.get("lat_samples", len(r["per_call"])))},
+                       "samples": int(r.get("lat_samples", len(r["per_call"]))),
+                       "launches_per_product": launches_per_product(g) if nv <= 4 else None},
         "variants": [{"nv": v, "precision": prec, "ms": round(res["t_ms"], 4),
                       "gflops": round(res["alg"]["flops"] / (res["t_ms"] * 1e-3) / 1e9, 2),
                       "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
                       "rel_err_vs_fp64": res.get("rel_err_vs_fp64"), "p99_ms": round(res["p99"], 4),
+                      "path_roofline": path_roofline(st, v, prec, res["t_ms"]),
                       "phases_ms": res["prof"]}
                      for (v, prec), res in results.items() if (v, prec) != (nv, "fp64")],
     }
