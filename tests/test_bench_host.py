@@ -1,0 +1,66 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU refusal, the algorithmic
+flop and byte counts, the whole-path roofline and the traffic lookup in the
+committed profile summaries."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def stats(**kw):
+    st = {"n": 1000, "tree_rows": 300, "entries_U": 0, "entries_V": 0, "entries_E": 0, "entries_F": 0,
+          "entries_S": 0, "entries_D": 0}
+    st.update(kw)
+    return st
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_flop_count_convention():
+    """2 nv flops per stored entry, plus n nv for alpha and 2 n nv when beta != 0."""
+    st = stats(entries_U=10, entries_V=20, entries_E=3, entries_F=4, entries_S=100, entries_D=50)
+    a = bench.algorithmic(st, 3)
+    assert a["flops"] == 2 * 3 * 187 + 1000 * 3
+    assert bench.algorithmic(st, 3, beta_nonzero=True)["flops"] == 2 * 3 * 187 + 3 * 1000 * 3
+    assert a["phase_flops"]["coupling"] == 2 * 3 * 100 and a["phase_flops"]["dense"] == 2 * 3 * 50
+    assert a["phase_bytes"]["coupling"] == 8 * 100 + 2 * 8 * 3 * 300
+
+
+def test_path_roofline_bytes_and_flops():
+    # nv = 1: 8 bytes and 2 flops per entry, far under every ridge: bound by HBM
+    st = stats(entries_S=10 ** 9, entries_D=10 ** 9)
+    r = bench.path_roofline(st, 1, "fp64", 10.0)
+    t_bytes = (16e9 + 8.0 * 1000 * 2 + 4 * 8.0 * 300) / 8e12 * 1e3
+    assert r["bound"] == "hbm" and abs(r["t_roof_ms"] - round(t_bytes, 4)) < 1e-4
+    assert abs(r["frac"] - round(r["t_roof_ms"] / 10.0, 4)) < 1e-4
+    # nv = 64 in BF16: the low-rank bytes shrink 4x, the FP64 dense flops set the bound
+    r16 = bench.path_roofline(st, 64, "bf16", 10.0)
+    t_flops = 2 * 64 * 1e9 / 2500e12 + 2 * 64 * 1e9 / 78.6e12
+    assert r16["bound"] == "flops" and abs(r16["t_roof_ms"] - round(t_flops * 1e3, 4)) < 1e-4
+
+
+def test_traffic_only_from_a_summary_of_the_same_kernel_source(tmp_path, monkeypatch):
+    src = tmp_path / "paper_2109_05451_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "h2_kernels.hip").write_bytes(b"// kernels\n")
+    md5 = hashlib.md5(b"// kernels\n").hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "k_rows_cfg_nv1.md").write_text(f"kernel_source_md5: `{md5}`\n\n"
+                                            "traffic_bytes_per_launch (coupling rows): 1.5e+09\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("cfg", 1, "coupling") == 1.5e9
+    assert bench.measured_traffic("cfg", 1, "dense") is None       # no figure for that launch
+    assert bench.measured_traffic("cfg", 64, "coupling") is None   # no summary for that workload
+    (src / "h2_kernels.hip").write_bytes(b"// kernels, changed\n")
+    assert bench.measured_traffic("cfg", 1, "coupling") is None    # taken on another kernel source
