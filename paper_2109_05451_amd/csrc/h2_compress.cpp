@@ -181,11 +181,23 @@ int launch_tasks(Ctx& C, const std::vector<T>& tasks, hipError_t (*fn)(const T*,
 
 int launch_gemm_tasks(Ctx& C, const std::vector<GemmTask>& tasks, const std::vector<GemmPair>& pairs) {
   if (tasks.empty()) return H2_OK;
+  int md = 1;
+  for (const GemmTask& t : tasks) md = std::max(md, std::max(t.m, t.n));
   GemmTask* dt = nullptr;
   GemmPair* dp = nullptr;
   RC(C.ar.upload(tasks, &dt, C.s));
   RC(C.ar.upload(pairs, &dp, C.s));
-  CK(launch_gemm(dt, (int64_t)tasks.size(), dp, C.s), "compression GEMM");
+  CK(launch_gemm(dt, (int64_t)tasks.size(), dp, C.s, md), "compression GEMM");
+  return H2_OK;
+}
+
+int launch_triple_tasks(Ctx& C, const std::vector<TripleTask>& tasks) {
+  if (tasks.empty()) return H2_OK;
+  int md = 1;
+  for (const TripleTask& t : tasks) md = std::max(md, std::max(std::max(t.a, t.b), t.k2));
+  TripleTask* d = nullptr;
+  RC(C.ar.upload(tasks, &d, C.s));
+  CK(launch_triple(d, (int64_t)tasks.size(), C.s, md), "compression triple product");
   return H2_OK;
 }
 
@@ -301,7 +313,7 @@ int transform_coupling(Ctx& C, const Tree& Xr, const Tree& Xc) {
     t.beta = 0.0;
     RC(add_triple(C, tt, t));
   }
-  return launch_tasks(C, tt, launch_triple);
+  return launch_triple_tasks(C, tt);
 }
 
 // ---- step 2: Gram matrices of the block rows (own blocks), then the downsweep
@@ -339,7 +351,7 @@ int reweight(Ctx& C, Tree& X, bool rows, bool cols) {
       t.beta = 1.0;
       RC(add_triple(C, tt, t));
     }
-    RC(launch_tasks(C, tt, launch_triple));
+    RC(launch_triple_tasks(C, tt));
   }
   return H2_OK;
 }
@@ -406,7 +418,7 @@ int truncate_level_direct(Ctx& C, Tree& X, int64_t l, double thr2) {
     sc.push_back(ScaleTask{Dz + off[p - b0], np, lam, (int32_t)np, (int32_t)np, (int32_t)p, 0});
   }
   RC(launch_gemm_tasks(C, g1, p1));
-  RC(launch_tasks(C, tt, launch_triple));
+  RC(launch_triple_tasks(C, tt));
   RC(launch_eigs(C, et));
   if (!cnt.empty()) {
     CountTask* d = nullptr;
@@ -764,7 +776,7 @@ int compress_impl(h2_op_s* h, double tau, hipStream_t s, h2_handle* out, h2_comp
       t.beta = 0.0;
       RC(add_triple(C, tt, t));
     }
-    RC(launch_tasks(C, tt, launch_triple));
+    RC(launch_triple_tasks(C, tt));
     std::vector<CopyTask> ct;
     for (int64_t l = 1; l <= q; ++l) {
       for (int64_t c = P.level_ptr[l]; c < P.level_ptr[l + 1]; ++c) {

@@ -94,8 +94,10 @@ struct CopyTask {  // dst (rows x cols) = trans ? src^T : src
 };
 
 hipError_t launch_qr(const QrTask* t, int64_t n, hipStream_t s);
-hipError_t launch_gemm(const GemmTask* t, int64_t n, const GemmPair* p, hipStream_t s);
-hipError_t launch_triple(const TripleTask* t, int64_t n, hipStream_t s);
+// maxdim: the largest output dimension over the tasks (and, for the triple
+// product, the inner dimension k2); it picks the tile, at most 64
+hipError_t launch_gemm(const GemmTask* t, int64_t n, const GemmPair* p, hipStream_t s, int maxdim);
+hipError_t launch_triple(const TripleTask* t, int64_t n, hipStream_t s, int maxdim);
 hipError_t launch_eig(const EigTask* t, int64_t n, int nmax, hipStream_t s);  // nmax: largest order
 hipError_t launch_mask_gram(const MaskTask* t, int64_t n, hipStream_t s);
 hipError_t launch_count(const CountTask* t, int64_t n, double thr2, int32_t* counts, hipStream_t s);

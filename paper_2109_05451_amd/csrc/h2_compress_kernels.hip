@@ -121,13 +121,16 @@ __global__ __launch_bounds__(kCT) void k_qr(const QrTask* __restrict__ tasks) {
 
 // ---------------------------------------------------------------------------
 // GEMM tiles: thread (ty, tx) = (tid / 16, tid % 16) owns rows ty + 16 i and
-// columns tx + 16 j (i, j < 4) of a 64 x 64 output; K in chunks of 32 staged
-// in LDS as sA[k][row], sB[k][col] (stride 65 against bank conflicts).
+// columns tx + 16 j (i, j < MI) of a 16 MI x 16 MI output (MI = 1..4, picked
+// per launch from its largest task, so 36 x 36 blocks take 48 x 48 tiles);
+// K in chunks of 32 staged in LDS as sA[k][row], sB[k][col] (odd stride
+// against bank conflicts).  Every output sums over k in the same order
+// whatever MI.
 constexpr int kKc = 32;
-constexpr int kLd = kTile + 1;
 
+template <int MI>
 struct GemmAcc {
-  double v[4][4];
+  double v[MI][MI];
 };
 
 __device__ inline double opA(const double* A, int64_t lda, bool t, int i, int k) {
@@ -135,46 +138,50 @@ __device__ inline double opA(const double* A, int64_t lda, bool t, int i, int k)
 }
 
 // acc += op(A) (a x K) * op(B) (K x b), operands in global memory
-__device__ void gemm_acc(GemmAcc& acc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
+template <int MI>
+__device__ void gemm_acc(GemmAcc<MI>& acc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
                          bool tb, int a, int b, int K, double* sA, double* sB) {
+  constexpr int TILE = 16 * MI, LD = TILE + 1;
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   for (int k0 = 0; k0 < K; k0 += kKc) {
     const int kc = min(kKc, K - k0);
     __syncthreads();
-    for (int e = tid; e < kKc * kTile; e += kCT) {
+    for (int e = tid; e < kKc * TILE; e += kCT) {
       // transposed operands: consecutive threads walk k (contiguous), else rows
       int kk, i;
-      if (ta) { i = e / kKc; kk = e - i * kKc; } else { kk = e / kTile; i = e - kk * kTile; }
-      sA[kk * kLd + i] = (kk < kc && i < a) ? opA(A, lda, ta, i, k0 + kk) : 0.0;
+      if (ta) { i = e / kKc; kk = e - i * kKc; } else { kk = e / TILE; i = e - kk * TILE; }
+      sA[kk * LD + i] = (kk < kc && i < a) ? opA(A, lda, ta, i, k0 + kk) : 0.0;
     }
-    for (int e = tid; e < kKc * kTile; e += kCT) {
+    for (int e = tid; e < kKc * TILE; e += kCT) {
       int kk, j;
-      if (tb) { kk = e / kTile; j = e - kk * kTile; } else { j = e / kKc; kk = e - j * kKc; }
+      if (tb) { kk = e / TILE; j = e - kk * TILE; } else { j = e / kKc; kk = e - j * kKc; }
       // op(B)[k][j] = tb ? B[j][k] : B[k][j]
-      sB[kk * kLd + j] = (kk < kc && j < b) ? (tb ? B[j + (int64_t)(k0 + kk) * ldb] : B[(k0 + kk) + (int64_t)j * ldb])
-                                            : 0.0;
+      sB[kk * LD + j] = (kk < kc && j < b) ? (tb ? B[j + (int64_t)(k0 + kk) * ldb] : B[(k0 + kk) + (int64_t)j * ldb])
+                                          : 0.0;
     }
     __syncthreads();
     for (int kk = 0; kk < kc; ++kk) {
-      double ar[4], br[4];
+      double ar[MI], br[MI];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ar[i] = sA[kk * kLd + ty + 16 * i];
+      for (int i = 0; i < MI; ++i) ar[i] = sA[kk * LD + ty + 16 * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) br[j] = sB[kk * kLd + tx + 16 * j];
+      for (int j = 0; j < MI; ++j) br[j] = sB[kk * LD + tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc.v[i][j] = fma(ar[i], br[j], acc.v[i][j]);
+        for (int j = 0; j < MI; ++j) acc.v[i][j] = fma(ar[i], br[j], acc.v[i][j]);
     }
   }
 }
 
-__device__ void gemm_store(const GemmAcc& acc, double* C, int64_t ldc, int a, int b, double alpha, double beta) {
+template <int MI>
+__device__ void gemm_store(const GemmAcc<MI>& acc, double* C, int64_t ldc, int a, int b, double alpha,
+                           double beta) {
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < MI; ++j) {
       const int row = ty + 16 * i, col = tx + 16 * j;
       if (row < a && col < b) {
         double* o = C + row + (int64_t)col * ldc;
@@ -183,67 +190,72 @@ __device__ void gemm_store(const GemmAcc& acc, double* C, int64_t ldc, int a, in
     }
 }
 
+template <int MI>
 __global__ __launch_bounds__(kCT) void k_gemm(const GemmTask* __restrict__ tasks, const GemmPair* __restrict__ pairs) {
-  __shared__ double sA[kKc * kLd];
-  __shared__ double sB[kKc * kLd];
+  constexpr int LD = 16 * MI + 1;
+  __shared__ double sA[kKc * LD];
+  __shared__ double sB[kKc * LD];
   const GemmTask T = tasks[blockIdx.x];
-  GemmAcc acc;
+  GemmAcc<MI> acc;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc.v[i][j] = 0.0;
+    for (int j = 0; j < MI; ++j) acc.v[i][j] = 0.0;
   for (int p = T.pbeg; p < T.pend; ++p) {
     const GemmPair P = pairs[p];
-    gemm_acc(acc, P.A, P.lda, P.flags & 1, P.B, P.ldb, P.flags & 2, T.m, T.n, P.k, sA, sB);
+    gemm_acc<MI>(acc, P.A, P.lda, P.flags & 1, P.B, P.ldb, P.flags & 2, T.m, T.n, P.k, sA, sB);
   }
-  gemm_store(acc, T.C, T.ldc, T.m, T.n, T.alpha, T.beta);
+  gemm_store<MI>(acc, T.C, T.ldc, T.m, T.n, T.alpha, T.beta);
 }
 
-// C (a x b) = beta C + L (a x k1) M (k1 x k2) R^T (R: b x k2)
+// C = beta C + op(L) M R^T: L M (a x k2) into LDS, then times R^T; the tile
+// covers a, b and k2
+template <int MI>
 __global__ __launch_bounds__(kCT) void k_triple(const TripleTask* __restrict__ tasks) {
-  __shared__ double sA[kKc * kLd];
-  __shared__ double sB[kKc * kLd];
-  __shared__ double sT[kTile * kLd];  // L M, column-major with stride kLd
+  constexpr int TILE = 16 * MI, LD = TILE + 1;
+  __shared__ double sA[kKc * LD];
+  __shared__ double sB[kKc * LD];
+  __shared__ double sT[TILE * LD];  // L M, column-major with stride LD
   const TripleTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  GemmAcc acc;
+  GemmAcc<MI> acc;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc.v[i][j] = 0.0;
-  gemm_acc(acc, T.L, T.ldl, T.flags & 1, T.M, T.ldm, false, T.a, T.k2, T.k1, sA, sB);
+    for (int j = 0; j < MI; ++j) acc.v[i][j] = 0.0;
+  gemm_acc<MI>(acc, T.L, T.ldl, T.flags & 1, T.M, T.ldm, false, T.a, T.k2, T.k1, sA, sB);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) sT[(ty + 16 * i) + (tx + 16 * j) * kLd] = acc.v[i][j];
+    for (int j = 0; j < MI; ++j) sT[(ty + 16 * i) + (tx + 16 * j) * LD] = acc.v[i][j];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc.v[i][j] = 0.0;
+    for (int j = 0; j < MI; ++j) acc.v[i][j] = 0.0;
   __syncthreads();
   // (L M) from LDS times R^T
   for (int k0 = 0; k0 < T.k2; k0 += kKc) {
     const int kc = min(kKc, T.k2 - k0);
     __syncthreads();
-    for (int e = tid; e < kKc * kTile; e += kCT) {
-      const int kk = e / kTile, j = e - kk * kTile;
-      sB[kk * kLd + j] = (kk < kc && j < T.b) ? T.R[j + (int64_t)(k0 + kk) * T.ldr] : 0.0;
+    for (int e = tid; e < kKc * TILE; e += kCT) {
+      const int kk = e / TILE, j = e - kk * TILE;
+      sB[kk * LD + j] = (kk < kc && j < T.b) ? T.R[j + (int64_t)(k0 + kk) * T.ldr] : 0.0;
     }
     __syncthreads();
     for (int kk = 0; kk < kc; ++kk) {
-      double ar[4], br[4];
+      double ar[MI], br[MI];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ar[i] = sT[(ty + 16 * i) + (k0 + kk) * kLd];
+      for (int i = 0; i < MI; ++i) ar[i] = sT[(ty + 16 * i) + (k0 + kk) * LD];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) br[j] = sB[kk * kLd + tx + 16 * j];
+      for (int j = 0; j < MI; ++j) br[j] = sB[kk * LD + tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc.v[i][j] = fma(ar[i], br[j], acc.v[i][j]);
+        for (int j = 0; j < MI; ++j) acc.v[i][j] = fma(ar[i], br[j], acc.v[i][j]);
     }
   }
-  gemm_store(acc, T.C, T.ldc, T.a, T.b, 1.0, T.beta);
+  gemm_store<MI>(acc, T.C, T.ldc, T.a, T.b, 1.0, T.beta);
 }
 
 // ---------------------------------------------------------------------------
@@ -446,14 +458,22 @@ hipError_t launch_qr(const QrTask* t, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_qr, grid_of(n), dim3(kCT), 0, s, t);
   return hipGetLastError();
 }
-hipError_t launch_gemm(const GemmTask* t, int64_t n, const GemmPair* p, hipStream_t s) {
+hipError_t launch_gemm(const GemmTask* t, int64_t n, const GemmPair* p, hipStream_t s, int maxdim) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm, grid_of(n), dim3(kCT), 0, s, t, p);
+  if (maxdim <= 16) hipLaunchKernelGGL((k_gemm<1>), grid_of(n), dim3(kCT), 0, s, t, p);
+  else if (maxdim <= 32) hipLaunchKernelGGL((k_gemm<2>), grid_of(n), dim3(kCT), 0, s, t, p);
+  else if (maxdim <= 48) hipLaunchKernelGGL((k_gemm<3>), grid_of(n), dim3(kCT), 0, s, t, p);
+  else if (maxdim <= kTile) hipLaunchKernelGGL((k_gemm<4>), grid_of(n), dim3(kCT), 0, s, t, p);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
-hipError_t launch_triple(const TripleTask* t, int64_t n, hipStream_t s) {
+hipError_t launch_triple(const TripleTask* t, int64_t n, hipStream_t s, int maxdim) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_triple, grid_of(n), dim3(kCT), 0, s, t);
+  if (maxdim <= 16) hipLaunchKernelGGL((k_triple<1>), grid_of(n), dim3(kCT), 0, s, t);
+  else if (maxdim <= 32) hipLaunchKernelGGL((k_triple<2>), grid_of(n), dim3(kCT), 0, s, t);
+  else if (maxdim <= 48) hipLaunchKernelGGL((k_triple<3>), grid_of(n), dim3(kCT), 0, s, t);
+  else if (maxdim <= kTile) hipLaunchKernelGGL((k_triple<4>), grid_of(n), dim3(kCT), 0, s, t);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 hipError_t launch_eig(const EigTask* t, int64_t n, int nmax, hipStream_t s) {
