@@ -1,7 +1,9 @@
 """Parity at full size for the 3D workload: N = 2^19 points uniform in [0,1]^3,
 leaf 64, kernel 1/(4 pi r) with zero diagonal, 4x4x4 Chebyshev (rank 64),
-eta 0.7, nv = 64 (the MFMA path).  Sampled output rows are computed one by one
-by the oracle and compared to the 1e-12 bar of the small parity tests."""
+eta 0.7, nv = 64 (the MFMA path), tuned as bench.py tunes it, in FP64 and in
+the BF16 and FP32 variants.  Sampled output rows are computed one by one by
+the oracle and compared to the bars of the small tests: 1e-12 * B (FP64),
+2e-5 * B (FP32), 5e-2 * B (BF16)."""
 import numpy as np
 import pytest
 
@@ -20,17 +22,24 @@ def test_full_size_3d_sampled_rows():
     Xh = h2gen.vectors(n, nv, 2003)
     X = torch.from_numpy(np.asfortranarray(Xh)).cuda()
     Y = torch.empty((nv, n), dtype=torch.float64, device="cuda").t()
+    stream = torch.cuda.current_stream().cuda_stream
     g.reserve(nv)
-    g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
-    got = Y.cpu().numpy()
+    got = {}
+    for prec in ("fp64", "bf16", "fp32"):
+        if prec != "fp64":
+            g.prepare(prec)
+        g.tune(nv, prec, stream)
+        g.gemv_raw("N", 1.0, X.data_ptr(), n, nv, 0.0, Y.data_ptr(), n, stream, prec)
+        torch.cuda.synchronize()
+        got[prec] = Y.cpu().numpy()
     g.close()
     del X, Y
     ref = oracle.Oracle(buf.array)
     rows = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(3).integers(0, n, 30)]))
     want = ref.gemv_rows(rows, Xh)
     B = ref.gemv_rows(rows, Xh, absval=True)
-    diff = np.abs(got[rows] - want)
-    assert np.all(diff <= 1e-12 * B), np.max(diff / B)
-    assert np.linalg.norm(got[rows] - want) <= 1e-12 * np.linalg.norm(want)
-    assert np.all(np.isfinite(got))
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5), ("bf16", 5e-2)):
+        diff = np.abs(got[prec][rows] - want)
+        assert np.all(diff <= tol * B), (prec, np.max(diff / B))
+        assert np.linalg.norm(got[prec][rows] - want) <= tol * np.linalg.norm(want), prec
+        assert np.all(np.isfinite(got[prec]))
