@@ -415,9 +415,11 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, con
 }
 
 // nvp > 0: MFMA path with nvp vectors per row (row-major workspace).
-// f32: the low-rank launches read the FP32 copy (the dense phase never does).
+// FP32: the low-rank launches read the FP32 copy of the data (the dense
+// phase never does); x32: a coupling launch that may gather x^ from its FP32
+// copy (filled by convert_xh32 after the upsweep).
 int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Epilogue& ep, hipStream_t s,
-               int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64) {
+               int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64, bool x32 = false) {
   double* bufs[4] = {w.xt, w.xh, w.yh, w.zn};
   const bool lowp = prec == H2_PREC_FP32 && L.lowrank && L.kind != KIND_WIDE;
   if (prec == H2_PREC_BF16 && L.lowrank && nvp > 0) {
@@ -440,9 +442,10 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   hipError_t e = hipSuccess;
   if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
+    const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
     e = lowp ? launch_rows_mfma<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
                                        data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
-                                       L.remapp[pi])
+                                       L.remapp[pi], in32)
              : launch_rows_mfma<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
                                         data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
                                         L.remapp[pi]);
@@ -547,8 +550,11 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   for (const Launch& L : dense1) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
   STEP(mark(9, w.side));
   for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
+  const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
+  if (x32) HIP_TRY(launch_to_f32(w.xh, w.xh32, h->H * (int64_t)nvp, s), "x^ to FP32");
   STEP(mark(2, s));
-  for (const Launch& L : couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  for (const Launch& L : couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec, x32));
   STEP(mark(3, s));
   // second half of the dense rows, beside the downsweep and the leaf expansion
   HIP_TRY(hipEventRecord(w.ev_mid, s), "hipEventRecord(mid)");
@@ -630,7 +636,8 @@ int h2_reserve(h2_handle h, int64_t nv_max) {
 namespace h2 {
 int64_t ws_bytes(int64_t n, int64_t H, int64_t cap) {
   return (int64_t)sizeof(double) *
-         (2 * std::max<int64_t>(n, 1) + std::max<int64_t>(H, 8) + std::max<int64_t>(H, 1)) * cap;
+             (2 * std::max<int64_t>(n, 1) + std::max<int64_t>(H, 8) + std::max<int64_t>(H, 1)) * cap +
+         (cap >= kPassVectorsMfma ? (int64_t)sizeof(float) * std::max<int64_t>(H, 1) * cap : 0);
 }
 
 int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
@@ -645,6 +652,8 @@ int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
           hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void**>(&w->yh), sizeof(double) * Hs * cap)) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void**>(&w->zn), sizeof(double) * nn * cap)) != hipSuccess ||
+      (cap >= kPassVectorsMfma &&
+       (e = hipMalloc(reinterpret_cast<void**>(&w->xh32), sizeof(float) * Hs * cap)) != hipSuccess) ||
       (e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming)) != hipSuccess ||
@@ -659,6 +668,7 @@ int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
 void ws_destroy(Workspace* w) {
   for (double* p : {w->xt, w->xh, w->yh, w->zn})
     if (p) (void)hipFree(p);
+  if (w->xh32) (void)hipFree(w->xh32);
   if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
   if (w->ev_join) (void)hipEventDestroy(w->ev_join);
   if (w->ev_mid) (void)hipEventDestroy(w->ev_mid);
@@ -778,7 +788,9 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   }
   const Epilogue ep{w.zn, h->d_perm, 1.0, 0.0, nullptr, 0, h->n};
   // best candidate of one launch; its time (ms, two timed runs) in *tbest
-  auto tune_one = [&](Launch& L, int mode_override, float* tbest) -> int {
+  if (w.xh32) HIP_TRY(hipMemsetAsync(w.xh32, 0, sizeof(float) * std::max<int64_t>(w.H, 1) * w.cap, s), "hipMemsetAsync");
+  const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
+  auto tune_one = [&](Launch& L, int mode_override, float* tbest, bool couple = false) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
     const int kcs[11] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8};  // 0: pipelined, 1-8: balanced (64 vectors only)
     const int64_t grids[4] = {0, 1024, 2048, 4096};
@@ -802,7 +814,8 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
           float tsum = 0.0f;
           for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
-            int r = run_launch(h, w, T, nvp, ep, s, nvp, mode_override, L.lowrank ? prec : H2_PREC_FP64);
+            int r = run_launch(h, w, T, nvp, ep, s, nvp, mode_override, L.lowrank ? prec : H2_PREC_FP64,
+                               couple && x32);
             if (r != H2_OK) return r;
             HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
             HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -826,11 +839,11 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     return H2_OK;
   };
   Plan& plan = h->planN;
-  auto tune_list = [&](std::vector<Launch>& v, float* total) -> int {
+  auto tune_list = [&](std::vector<Launch>& v, float* total, bool couple = false) -> int {
     *total = 0.0f;
     for (Launch& L : v) {
       float t = 0.0f;
-      const int r = tune_one(L, -1, &t);
+      const int r = tune_one(L, -1, &t, couple);
       if (r != H2_OK) return r;
       *total += t;
     }
@@ -839,8 +852,8 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   float t_up = 0, t_down = 0, tc = 0, tcl = 0, td1 = 0, td2 = 0, tl1 = 0, tl2 = 0;
   rc = tune_list(plan.up, &t_up);
   if (rc == H2_OK) rc = tune_list(plan.down, &t_down);
-  if (rc == H2_OK) rc = tune_list(plan.couple, &tc);
-  if (rc == H2_OK) rc = tune_list(plan.couple_loc, &tcl);
+  if (rc == H2_OK) rc = tune_list(plan.couple, &tc, true);
+  if (rc == H2_OK) rc = tune_list(plan.couple_loc, &tcl, true);
   if (rc == H2_OK) rc = tune_list(plan.dense, &td1);
   if (rc == H2_OK) rc = tune_list(plan.dense2, &td2);
   if (rc == H2_OK) rc = tune_list(plan.dense_loc, &tl1);

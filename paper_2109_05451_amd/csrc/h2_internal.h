@@ -202,6 +202,9 @@ int64_t row_work(const RowSpec& r);
 struct Workspace {
   int64_t n = 0, H = 0, cap = 0;
   double *xt = nullptr, *xh = nullptr, *yh = nullptr, *zn = nullptr;
+  // FP32 copy of x^ (H * cap floats; cap >= kPassVectorsMfma only) that the
+  // FP32 variant's 64-vector coupling launches gather from
+  float* xh32 = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
 };
@@ -274,7 +277,8 @@ hipError_t launch_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend
 template <typename T>
 hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int kc = 64, int64_t grid = 0, int remap = 0);
+                            hipStream_t s, int kc = 64, int64_t grid = 0, int remap = 0,
+                            const float* in32 = nullptr);
 
 // One operator's part of a batched call, as the batched permutation kernels see it.
 struct BatchItem {

@@ -16,6 +16,7 @@
 // kernel; only the epilogue differs (store, accumulate, or the final
 // permuted alpha/beta update).
 #include <algorithm>
+#include <type_traits>
 
 #include "h2_internal.h"
 
@@ -228,45 +229,71 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // are accessed with coalesced loads and stores.
 constexpr int kPermTile = 64;
 
-// xt[pinv[j], v] = X[j, v] for v < nv, 0 for nv <= v < nvp.
+// xt[pinv[j], v] = X[j, v] for v < nv, 0 for nv <= v < NVP.  A workgroup
+// moves kPermTile original rows through LDS: every thread issues all of its
+// coalesced column loads first (PER of them, unrolled), then the wave-wide
+// row stores follow.
+template <int NVP>
 __global__ __launch_bounds__(256) void k_permute_in_rm(const double* __restrict__ X, int64_t ldx,
                                                        const int32_t* __restrict__ pinv, double* __restrict__ xt,
-                                                       int64_t n, int nv, int nvp) {
-  __shared__ double tile[kPermTile * (kPassVectorsMfma + 1)];
-  constexpr int LD = kPassVectorsMfma + 1;
+                                                       int64_t n, int nv) {
+  constexpr int LD = NVP + 1, PER = kPermTile * NVP / 256;
+  __shared__ double tile[kPermTile * LD];
   const int64_t j0 = blockIdx.x * (int64_t)kPermTile;
   const int rows = (int)min<int64_t>(kPermTile, n - j0);
-  for (int e = threadIdx.x; e < kPermTile * nvp; e += blockDim.x) {
-    const int v = e / kPermTile, jj = e - v * kPermTile;
-    if (jj < rows) tile[jj * LD + v] = v < nv ? X[j0 + jj + ldx * v] : 0.0;
+  double r[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    r[i] = jj < rows && v < nv ? __builtin_nontemporal_load(X + j0 + jj + ldx * v) : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    tile[jj * LD + v] = r[i];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kPermTile * nvp; e += blockDim.x) {
-    const int jj = e / nvp, v = e - jj * nvp;
-    if (jj < rows) xt[(int64_t)pinv[j0 + jj] * nvp + v] = tile[jj * LD + v];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    if (jj < rows) xt[(int64_t)pinv[j0 + jj] * NVP + v] = tile[jj * LD + v];
   }
 }
 
-// Y[j, v] = alpha * Z[pinv[j], v] + beta * Y[j, v] (Z row-major nvp, tree order).
+// Y[j, v] = alpha * Z[pinv[j], v] + beta * Y[j, v] (Z row-major NVP, tree
+// order), the same way round: row gathers into LDS, column stores out.
+template <int NVP>
 __global__ __launch_bounds__(256) void k_permute_out_rm(const double* __restrict__ Z,
                                                         const int32_t* __restrict__ pinv, double alpha, double beta,
-                                                        double* __restrict__ Y, int64_t ldy, int64_t n, int nv,
-                                                        int nvp) {
-  __shared__ double tile[kPermTile * (kPassVectorsMfma + 1)];
-  constexpr int LD = kPassVectorsMfma + 1;
+                                                        double* __restrict__ Y, int64_t ldy, int64_t n, int nv) {
+  constexpr int LD = NVP + 1, PER = kPermTile * NVP / 256;
+  __shared__ double tile[kPermTile * LD];
   const int64_t j0 = blockIdx.x * (int64_t)kPermTile;
   const int rows = (int)min<int64_t>(kPermTile, n - j0);
-  for (int e = threadIdx.x; e < kPermTile * nvp; e += blockDim.x) {
-    const int jj = e / nvp, v = e - jj * nvp;
-    if (jj < rows && v < nv) tile[jj * LD + v] = Z[(int64_t)pinv[j0 + jj] * nvp + v];
+  double r[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    r[i] = jj < rows && v < nv ? __builtin_nontemporal_load(Z + (int64_t)pinv[j0 + jj] * NVP + v) : 0.0;
+  }
+  double yv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    yv[i] = beta != 0.0 && jj < rows && v < nv ? Y[j0 + jj + ldy * v] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    tile[jj * LD + v] = r[i];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kPermTile * nv; e += blockDim.x) {
-    const int v = e / kPermTile, jj = e - v * kPermTile;
-    if (jj < rows) {
-      double* y = Y + j0 + jj + ldy * v;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    if (jj < rows && v < nv) {
       const double z = alpha * tile[jj * LD + v];
-      *y = beta == 0.0 ? z : z + beta * *y;
+      Y[j0 + jj + ldy * v] = beta == 0.0 ? z : z + beta * yv[i];
     }
   }
 }
@@ -534,12 +561,15 @@ __global__ __launch_bounds__(kT) void k_rows_mfma_pipe(const RowDesc* __restrict
 // chunk's MFMAs and stored after them, with one barrier per chunk.  OCC > 1
 // asks the compiler for registers enough for OCC workgroups per CU (four fit
 // the 16-column chunk's LDS, more the 8-column one's), trading a little
-// spilling for latency hiding.
-template <typename T, int KC, bool DEEP, int MT, int OCC>
+// spilling for latency hiding.  The gathered input is read as TI: FP64, or
+// FP32 in the FP32 variant's coupling launches.  With FP32 data each
+// gathered value is rounded to FP32 anyway, so gathering from a rounded copy
+// of x^ gives the same products from half the bytes.
+template <typename T, typename TI, int KC, bool DEEP, int MT, int OCC>
 __global__ __launch_bounds__(kT, OCC) void k_rows_mfma_bal(const RowDesc* __restrict__ rows, int64_t nrows,
                                                       const int32_t* __restrict__ colend,
                                                       const int64_t* __restrict__ in_off,
-                                                      const T* __restrict__ data, const double* in, double* out,
+                                                      const T* __restrict__ data, const TI* in, double* out,
                                                       int mode, int remap) {
   typedef typename MfmaAcc<T>::t CT;
   constexpr int NVP = 64, LDA = 68, LDB = 66;  // padded LDS rows (doubles or floats)
@@ -803,7 +833,7 @@ template hipError_t launch_rows<float>(const RowDesc*, int64_t, const int32_t*, 
 template <typename T>
 hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int kc, int64_t grid, int remap) {
+                            hipStream_t s, int kc, int64_t grid, int remap, const float* in32) {
   if (nrows == 0) return hipSuccess;
   const dim3 g((unsigned)grid_of_rows(nrows, grid, remap)), block(kT);
 #define H2_MFMA3(NT, MAXT, KC)                                                                                   \
@@ -824,12 +854,23 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
   // issued two chunks ahead; 5, 6: balanced, 16 columns (loads one or two
   // chunks ahead) with registers for four workgroups per CU; 7, 8: the same
   // with 8 columns and five workgroups per CU (0-8 take 64 vectors, 1-8 rows
-  // of at most 64 outputs; other launches fall back to 64 columns)
+  // of at most 64 outputs; other launches fall back to 64 columns).  in32:
+  // an FP32 copy of the input that the balanced kernels read instead (FP32
+  // data only; null: read in)
   if ((kc == 0 && nvp != 64) || ((kc >= 1 && kc <= 8) && (nvp != 64 || max_rows > 64))) kc = 64;
   if (kc >= 1 && kc <= 8) {
-#define H2_BAL(KCV, DEEP, MT, OCC)                                                                      \
-  hipLaunchKernelGGL((k_rows_mfma_bal<T, KCV, DEEP, MT, OCC>), g, block, 0, s, rows, nrows, colend, in_off, \
-                     data, in, out, mode, remap)
+#define H2_BAL(KCV, DEEP, MT, OCC)                                                                           \
+  do {                                                                                                       \
+    if constexpr (std::is_same<T, float>::value) {                                                           \
+      if (in32) {                                                                                            \
+        hipLaunchKernelGGL((k_rows_mfma_bal<T, float, KCV, DEEP, MT, OCC>), g, block, 0, s, rows, nrows, colend, \
+                           in_off, data, in32, out, mode, remap);                                           \
+        break;                                                                                               \
+      }                                                                                                      \
+    }                                                                                                        \
+    hipLaunchKernelGGL((k_rows_mfma_bal<T, double, KCV, DEEP, MT, OCC>), g, block, 0, s, rows, nrows, colend,  \
+                       in_off, data, in, out, mode, remap);                                                 \
+  } while (0)
 #define H2_BAL_MT(KCV, DEEP, OCC)                       \
   do {                                                  \
     if (max_rows <= 16) H2_BAL(KCV, DEEP, 1, OCC);      \
@@ -870,9 +911,12 @@ hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* c
   return hipGetLastError();
 }
 template hipError_t launch_rows_mfma<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
-                                             const double*, double*, int, int, int, hipStream_t, int, int64_t, int);
+                                             const double*, double*, int, int, int, hipStream_t, int, int64_t, int,
+                                             const float*);
 template hipError_t launch_rows_mfma<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
-                                            const double*, double*, int, int, int, hipStream_t, int, int64_t, int);
+                                            const double*, double*, int, int, int, hipStream_t, int, int64_t, int,
+                                            const float*);
+
 
 // Batched input permutation: operator blockIdx.y, original index j.  Rows
 // of the workspace arena are row-major with nvp vectors; padding vectors,
@@ -1147,7 +1191,14 @@ hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pin
                                 int nvp, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (nvp > kPassVectorsMfma || nv > nvp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_permute_in_rm, dim3(grid1d(n, kPermTile)), dim3(256), 0, s, X, ldx, pinv, xt, n, nv, nvp);
+  const dim3 g(grid1d(n, kPermTile)), b(256);
+  switch (nvp) {
+    case 16: hipLaunchKernelGGL(k_permute_in_rm<16>, g, b, 0, s, X, ldx, pinv, xt, n, nv); break;
+    case 32: hipLaunchKernelGGL(k_permute_in_rm<32>, g, b, 0, s, X, ldx, pinv, xt, n, nv); break;
+    case 48: hipLaunchKernelGGL(k_permute_in_rm<48>, g, b, 0, s, X, ldx, pinv, xt, n, nv); break;
+    case 64: hipLaunchKernelGGL(k_permute_in_rm<64>, g, b, 0, s, X, ldx, pinv, xt, n, nv); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1155,8 +1206,14 @@ hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double al
                                  int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (nvp > kPassVectorsMfma || nv > nvp) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_permute_out_rm, dim3(grid1d(n, kPermTile)), dim3(256), 0, s, Z, pinv, alpha, beta, Y, ldy, n,
-                     nv, nvp);
+  const dim3 g(grid1d(n, kPermTile)), b(256);
+  switch (nvp) {
+    case 16: hipLaunchKernelGGL(k_permute_out_rm<16>, g, b, 0, s, Z, pinv, alpha, beta, Y, ldy, n, nv); break;
+    case 32: hipLaunchKernelGGL(k_permute_out_rm<32>, g, b, 0, s, Z, pinv, alpha, beta, Y, ldy, n, nv); break;
+    case 48: hipLaunchKernelGGL(k_permute_out_rm<48>, g, b, 0, s, Z, pinv, alpha, beta, Y, ldy, n, nv); break;
+    case 64: hipLaunchKernelGGL(k_permute_out_rm<64>, g, b, 0, s, Z, pinv, alpha, beta, Y, ldy, n, nv); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
