@@ -395,9 +395,12 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, con
   if (device < 0 || device >= ndev) { set_error("device ordinal out of range"); return H2_EINVAL; }
   DeviceGuard guard(device);
   if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  int ncu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
   h2_op_s* h = new (std::nothrow) h2_op_s();
   if (!h) { set_error("out of host memory"); return H2_ENOMEM; }
   h->device = device;
+  h->dense_stream_grid = 2 * (int64_t)std::max(ncu, 1);
   try {
     rc = build_handle(buf, P, h, d_dense);
     h->file_len = len;
@@ -450,10 +453,13 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
                                         data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
                                         L.remapp[pi]);
   } else if (L.kind == KIND_STREAM) {
+    // the dense rows (beside the sweeps) hold two workgroup slots per CU, so
+    // the sweeps' small launches find free slots at once
+    const int64_t sg = L.lowrank ? 0 : h->dense_stream_grid;
     e = lowp ? launch_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off, data32,
-                                  bufs[L.in], out, nv, mode, ep, s)
+                                  bufs[L.in], out, nv, mode, ep, s, sg)
              : launch_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off, data,
-                                   bufs[L.in], out, nv, mode, ep, s);
+                                   bufs[L.in], out, nv, mode, ep, s, sg);
   } else if (L.kind == KIND_WIDE) {
     e = launch_rows_wide(h->wide.d_rows + L.row_begin, L.row_count, h->wide.d_colend, h->wide.d_in_off, data,
                          bufs[L.in], out, nv, s);

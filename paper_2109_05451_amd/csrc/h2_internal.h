@@ -244,6 +244,9 @@ struct h2_op_s {
   int32_t* d_perm = nullptr;
   int32_t* d_pinv = nullptr;  // original index -> tree position
   bool mfma_ok = true;        // every op-'N' launch fits the MFMA row kernel
+  // workgroups of the dense launches on the streaming path (nv <= 4): two per
+  // CU, a persistent grid that leaves the other slots to the sweeps beside it
+  int64_t dense_stream_grid = 0;
   int couple_mode[3] = {0, 0, 0};  // per precision: 0 longest first, 1 tree order (h2_tune)
   int dense_mode[3] = {0, 0, 0};   // per precision: 0 longest first, 1 tree order (h2_tune)
   h2::RowTables rt;           // streaming rows of both plans
@@ -273,7 +276,7 @@ hipError_t launch_scale(double* Y, int64_t ldy, int64_t n, int64_t nv, double be
 template <typename T>
 hipError_t launch_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                        const T* data, const double* in, double* out, int nv, int mode, const Epilogue& ep,
-                       hipStream_t s);
+                       hipStream_t s, int64_t grid = 0);
 template <typename T>
 hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,

@@ -104,8 +104,11 @@ __device__ __forceinline__ void stream_cols(const T* __restrict__ Mrow, int64_t 
 // Y[perm[i]] = alpha*(s + zn[i]) + beta*Y[perm[i]] (in FP64).
 // T = double: the FP64 path; T = float: the low-rank phases of the FP32
 // path (vector trees stay FP64 in memory; products accumulate in FP32).
+// Rows are taken grid-stride: one workgroup per row, or fewer workgroups
+// that each take several rows (a launch that holds only part of every CU).
 template <typename T, int NVB>
-__global__ __launch_bounds__(kT) void k_rows(const RowDesc* __restrict__ rows, const int32_t* __restrict__ colend,
+__global__ __launch_bounds__(kT) void k_rows(const RowDesc* __restrict__ rows, int64_t nrows,
+                                             const int32_t* __restrict__ colend,
                                              const int64_t* __restrict__ in_off, const T* __restrict__ data,
                                              const double* in, double* out, int nv, int mode, Epilogue ep) {
   typedef typename Acc<T>::t A;
@@ -114,9 +117,11 @@ __global__ __launch_bounds__(kT) void k_rows(const RowDesc* __restrict__ rows, c
   __shared__ A xs[XS * NVB];
   __shared__ int32_t s_end[kNbMax];
   __shared__ int64_t s_in[kNbMax];
-  const RowDesc R = rows[blockIdx.x];
+  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+  __syncthreads();  // LDS of the previous row fully consumed
+  const RowDesc R = rows[ri];
   const int m = R.nrows;
-  if (m <= 0) return;
+  if (m <= 0) continue;
   const int tid = threadIdx.x;
   const int nb = R.blk_end - R.blk_begin;  // <= kNbMax, checked when the schedule is built
   for (int i = tid; i < nb; i += kT) {
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(kT) void k_rows(const RowDesc* __restrict__ rows, c
       *y = ep.beta == 0.0 ? ep.alpha * s : ep.alpha * s + ep.beta * *y;
     }
   }
+  }  // rows
 }
 
 // Rows with more blocks than the LDS tables hold: one thread per output row
@@ -812,23 +818,23 @@ hipError_t launch_scale(double* Y, int64_t ldy, int64_t n, int64_t nv, double be
 template <typename T>
 hipError_t launch_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                        const T* data, const double* in, double* out, int nv, int mode, const Epilogue& ep,
-                       hipStream_t s) {
+                       hipStream_t s, int64_t grid) {
   if (nrows == 0) return hipSuccess;
-  const dim3 grid((unsigned)nrows), block(kT);
+  const dim3 g((unsigned)(grid > 0 && grid < nrows ? grid : nrows)), block(kT);
   if (nv <= 1)
-    hipLaunchKernelGGL((k_rows<T, 1>), grid, block, 0, s, rows, colend, in_off, data, in, out, nv, mode, ep);
+    hipLaunchKernelGGL((k_rows<T, 1>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, nv, mode, ep);
   else if (nv == 2)
-    hipLaunchKernelGGL((k_rows<T, 2>), grid, block, 0, s, rows, colend, in_off, data, in, out, nv, mode, ep);
+    hipLaunchKernelGGL((k_rows<T, 2>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, nv, mode, ep);
   else if (nv <= 4)
-    hipLaunchKernelGGL((k_rows<T, 4>), grid, block, 0, s, rows, colend, in_off, data, in, out, nv, mode, ep);
+    hipLaunchKernelGGL((k_rows<T, 4>), g, block, 0, s, rows, nrows, colend, in_off, data, in, out, nv, mode, ep);
   else
     return hipErrorInvalidValue;  // callers pass at most kPassVectors vectors
   return hipGetLastError();
 }
 template hipError_t launch_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
-                                        const double*, double*, int, int, const Epilogue&, hipStream_t);
+                                        const double*, double*, int, int, const Epilogue&, hipStream_t, int64_t);
 template hipError_t launch_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
-                                       const double*, double*, int, int, const Epilogue&, hipStream_t);
+                                       const double*, double*, int, int, const Epilogue&, hipStream_t, int64_t);
 
 template <typename T>
 hipError_t launch_rows_mfma(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,

@@ -38,13 +38,20 @@ def test_fp32_integer_bitwise(case):
         g = H2Operator(buf)
         g.prepare("fp32")
         rng = np.random.default_rng(seed)
-        for nv in (1, 4, 17):
+        for nv in (1, 4, 17, 64):
             X = rng.integers(-2, 3, size=(g.n, nv)).astype(np.float64)
             Y0 = rng.integers(-2, 3, size=(g.n, nv)).astype(np.float64)
             for op in "NT":
                 want = ref.gemv(X, op=op, alpha=2.0, beta=-1.0, Y=Y0)
                 got = run(g, X, op, 2.0, -1.0, Y0)
                 assert np.array_equal(got, want), (case, seed, nv, op)
+                if nv == 64 and op == "N":
+                    # the balanced kernels, whose coupling launches gather
+                    # from the FP32 copy of x^
+                    g.tune_set("fp32", 8)
+                    got = run(g, X, op, 2.0, -1.0, Y0)
+                    g.tune_set("fp32", 64)
+                    assert np.array_equal(got, want), (case, seed, nv, op, "kc 8")
         g.close()
 
 
