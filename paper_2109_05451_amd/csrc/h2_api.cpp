@@ -420,7 +420,7 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, con
 // nvp > 0: MFMA path with nvp vectors per row (row-major workspace).
 // FP32: the low-rank launches read the FP32 copy of the data (the dense
 // phase never does); x32: a coupling launch that may gather x^ from its FP32
-// copy (filled by convert_xh32 after the upsweep).
+// copy (w.xh32, converted from w.xh after the upsweep).
 int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Epilogue& ep, hipStream_t s,
                int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64, bool x32 = false) {
   double* bufs[4] = {w.xt, w.xh, w.yh, w.zn};
@@ -793,9 +793,11 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     return H2_EHIP;
   }
   const Epilogue ep{w.zn, h->d_perm, 1.0, 0.0, nullptr, 0, h->n};
-  // best candidate of one launch; its time (ms, two timed runs) in *tbest
-  if (w.xh32) HIP_TRY(hipMemsetAsync(w.xh32, 0, sizeof(float) * std::max<int64_t>(w.H, 1) * w.cap, s), "hipMemsetAsync");
+  if (w.xh32)
+    HIP_TRY(hipMemsetAsync(w.xh32, 0, sizeof(float) * std::max<int64_t>(w.H, 1) * w.cap, s), "hipMemsetAsync");
+  // FP32 at 64 vectors: the coupling candidates gather from the FP32 copy of x^
   const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
+  // best candidate of one launch; its time (ms, two timed runs) in *tbest
   auto tune_one = [&](Launch& L, int mode_override, float* tbest, bool couple = false) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
     const int kcs[11] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8};  // 0: pipelined, 1-8: balanced (64 vectors only)
