@@ -314,6 +314,12 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// Four 4x4x4 FP64 products in one instruction.  Lane 16k + 4*blk + i holds
+// A_blk[i][k], lane 16k + 4*blk + j holds B_blk[k][j], and the result of
+// lane 16i + 4*blk + j is D_blk[i][j].
+__device__ __forceinline__ double mfma4x4x4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 
 // T = double: FP64 MFMA; T = float: FP32 MFMA on the FP32 copy of the
 // low-rank data (inputs rounded to FP32 when staged, FP32 accumulation).
@@ -608,6 +614,15 @@ __global__ __launch_bounds__(kT, OCC) void k_rows_mfma_bal(const RowDesc* __rest
     CT acc[MT];
 #pragma unroll
     for (int i = 0; i < MT; ++i) acc[i] = CT{0, 0, 0, 0};
+    // FP64 rows of 33-36 outputs (rank 36): rows 32-35 go through the 4x4x4
+    // instruction (its four blocks are four 4-vector groups sharing the same
+    // A rows) instead of a 16-row tile that is three quarters padding.  Not
+    // in the one-workgroup-per-CU forms: compiled there, the extra
+    // accumulator lands in an AGPR that the epilogue read before the MFMA's
+    // result wait states.
+    constexpr bool kTail4 = sizeof(T) == 8 && MT == 3 && OCC > 1;
+    const bool tail4 = kTail4 && m > 32 && m <= 36;
+    double acc4 = 0.0;
     const int arow = lane & 15, akk = lane >> 4;
     const T* M = data + R.data_off;
     int bw = 0;
@@ -662,8 +677,16 @@ __global__ __launch_bounds__(kT, OCC) void k_rows_mfma_bal(const RowDesc* __rest
           const int k = 4 * u + akk;
           const T b = B[k * LDB + 16 * wave + arow];
 #pragma unroll
-          for (int ti = 0; ti < MT; ++ti)
-            if (ti < mt) acc[ti] = mfma16x16x4(A[k * LDA + 16 * ti + arow], b, acc[ti]);
+          for (int ti = 0; ti < MT; ++ti) {
+            if (ti >= mt) continue;
+            if constexpr (kTail4) {
+              if (ti == 2 && tail4) {
+                acc4 = mfma4x4x4(A[k * LDA + 32 + (arow & 3)], b, acc4);
+                continue;
+              }
+            }
+            acc[ti] = mfma16x16x4(A[k * LDA + 16 * ti + arow], b, acc[ti]);
+          }
         }
       }
     };
@@ -704,6 +727,15 @@ __global__ __launch_bounds__(kT, OCC) void k_rows_mfma_bal(const RowDesc* __rest
 #pragma unroll
     for (int ti = 0; ti < MT; ++ti) {
       if (ti >= mt) break;
+      if (ti == 2 && tail4) {
+        const int a = 32 + akk;  // row of this lane's 4x4x4 result
+        if (a < m) {
+          double* o = out + (R.out_off + a) * NVP + 16 * wave + arow;
+          if (mode == MODE_STORE) *o = acc4;
+          else *o += acc4;
+        }
+        continue;
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = ti * 16 + (sizeof(T) == 8 ? 4 * r + akk : 4 * akk + r);
