@@ -60,3 +60,28 @@ def test_rows_wider_than_the_block_table():
     buf = h2gen.random_rep(92, q=10, max_children=3, max_leaf=2, max_rank=2, p_adm=0.05, integer=True)
     info = check_bitwise(buf, (1, 3, 9))
     assert "kind=2" in info  # some dense rows (945 blocks) took the wide-row kernel
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_ranks_33_to_36_every_kernel(seed):
+    """Rows of 33-36 outputs take the 4x4x4 MFMA for their last four rows in
+    the balanced kernels' four- and five-workgroup forms.  Ranks 33-36 per
+    level (separate row and column bases) and leaves of 1-40 points mix such
+    rows with shorter and longer ones in one launch; at 64 vectors every
+    kernel setting must give the oracle's integer result bit for bit."""
+    from paper_2109_05451_amd import H2Operator
+    buf = h2gen.random_rep(seed, q=3, max_children=3, max_leaf=40, ranks=([34, 33, 35, 36], [36, 35, 33, 34]),
+                           p_adm=0.4, integer=True, int_range=1, allow_empty=False)
+    ref = oracle.Oracle(buf)
+    g = H2Operator(buf)
+    rng = np.random.default_rng(seed)
+    X = rng.integers(-2, 3, size=(g.n, 64)).astype(np.float64)
+    Y0 = rng.integers(-2, 3, size=(g.n, 64)).astype(np.float64)
+    want = ref.gemv(X, op="N", alpha=2.0, beta=-1.0, Y=Y0)
+    for kc in (0, 1, 2, 3, 4, 5, 6, 7, 8, 32, 64):
+        for grid in (0, 1024):
+            g.tune_set("fp64", kc, grid, False, 0)
+            got = run(g, X, "N", 2.0, -1.0, Y0)
+            assert np.array_equal(got, want), (seed, kc, grid)
+    g.close()
+    ref.close()
