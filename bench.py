@@ -89,6 +89,55 @@ def path_roofline(st: dict, nv: int, precision: str, t_ms: float) -> dict:
             "frac": round(t_roof * 1e3 / t_ms, 4)}
 
 
+PEAK_TFLOPS = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}
+ELEM_BYTES = {"fp64": 8.0, "fp32": 4.0, "bf16": 2.0}
+
+
+def coupling_roofline(st: dict, nv: int, precision: str, t_ms: float) -> dict:
+    """Roofline of the coupling launch (all levels' S x^ in one launch, the
+    largest single launch of every multi-vector run) at a precision: the
+    stored blocks and the vector trees (x^ read, y^ written) at that
+    precision's width.  Bound by HBM when its arithmetic intensity is under
+    the precision's ridge (peak / 8 TB/s), else by the matrix-core peak."""
+    w = ELEM_BYTES[precision]
+    bytes_ = w * st["entries_S"] + 2 * w * nv * st["tree_rows"]
+    flops = 2.0 * nv * st["entries_S"]
+    peak = PEAK_TFLOPS[precision]
+    if flops / bytes_ >= peak * 1e12 / (HBM_PEAK_GBS * 1e9):
+        achieved = flops / (t_ms * 1e-3) / 1e12
+        out = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s"}
+    else:
+        achieved = bytes_ / (t_ms * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    out.update({"frac": round(achieved / out["peak"], 4), "kernel": f"coupling rows ({precision}, nv={nv})",
+                "bytes_per_launch": bytes_, "flops_per_launch": flops, "ms_per_launch": round(t_ms, 4)})
+    return out
+
+
+def sample_rows(n: int, seed: int, count: int = 192) -> np.ndarray:
+    """Output rows whose values the oracle computes one by one (both ends,
+    the middle and a seeded uniform sample)."""
+    return np.unique(np.concatenate([[0, n // 2, n - 1], np.random.default_rng(seed).integers(0, n, count)]))
+
+
+def measured_copy_gbs(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """HBM bandwidth of a plain device-to-device copy (bytes read + written
+    per second), the measured counterpart of the 8 TB/s datasheet figure."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
 def launches_per_product(g) -> int:
     """Kernel launches of one single-vector product: the plan's upsweep,
     coupling, downsweep and dense launches, the leaf expansion and the input
@@ -430,6 +479,7 @@ def main():
     ap.add_argument("--nv", type=int, default=None, help="vectors of the headline run (default: config's first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="leave out the 3D workload beside the 2D one")
     ap.add_argument("--latency-calls", type=int, default=100,
                     help="individually timed calls of the headline run for p50/p99 (0: use the timed steps)")
     ap.add_argument("--batch-count", type=int, default=256, help="operators of the batched workload")
@@ -461,50 +511,22 @@ def main():
     if args.config == "c6_compress":
         print(json.dumps(bench_compress(args, torch)), flush=True)
         return
+    copy_gbs = measured_copy_gbs(torch)
+    print(f"# measured device copy: {copy_gbs:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
     import h2gen
-    from paper_2109_05451_amd import H2Operator
-
     cfg = h2gen.CONFIGS[args.config]
     nv = args.nv or cfg["nv"][0]
-    t0 = time.perf_counter()
-    buf = h2gen.build_config(args.config)
-    t_build = time.perf_counter() - t0
-    print(f"# built {args.config}: {buf.nbytes / 1e9:.2f} GB in {t_build:.1f} s", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    g = H2Operator(buf.array, device=0)
-    t_load = time.perf_counter() - t0
-    st = g.stats()
-    print(f"# loaded in {t_load:.1f} s; stats {st}", file=sys.stderr, flush=True)
-
     runs = [(nv, "fp64")]
     if not args.no_variants:
         runs += [(v, "fp64") for v in cfg["nv"] if v != nv]
         runs += [(v, p) for v in cfg["nv"] for p in cfg.get("precisions", ("fp32",))]
-    results, ref_out = {}, {}
-    for v, prec in runs:
-        Xh = h2gen.vectors(g.n, v, cfg["seed_vec"])
-        X = torch.from_numpy(np.asfortranarray(Xh)).cuda()
-        Y = torch.empty((v, g.n), dtype=torch.float64, device="cuda").t()
-        wall, per_call, prof = time_gpu(g, X, Y, v, args.steps, args.warmup, torch, prec)
-        alg = algorithmic(st, v)
-        srt = np.sort(per_call)
-        trimmed = srt[1:-1] if srt.size > 2 else srt  # the paper drops the fastest and the slowest
-        t_ms = float(np.mean(trimmed))
-        phases = {k[3:]: prof[k] / prof["calls"] for k in prof if k.startswith("ms_")}
-        res = dict(wall=wall, per_call=per_call, t_ms=t_ms, prof=phases, alg=alg,
-                   p50=float(np.percentile(per_call, 50)), p99=float(np.percentile(per_call, 99)))
-        if (v, prec) == (nv, "fp64") and args.latency_calls > 0:
-            lat = latency_gpu(g, X, Y, v, args.latency_calls, torch)
-            res.update(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)), lat_samples=lat.size)
-        Yh = Y.cpu().numpy()
-        if prec == "fp64":
-            ref_out[v] = Yh
-        elif v in ref_out:
-            res["rel_err_vs_fp64"] = float(np.linalg.norm(Yh - ref_out[v]) / np.linalg.norm(ref_out[v]))
-        results[(v, prec)] = res
-        print(f"# nv={v} {prec}: {t_ms:.3f} ms/call, phases {phases}", file=sys.stderr, flush=True)
-        del X, Y
+    work = [run_workload(args.config, runs, args, torch, latency_for=(nv, "fp64"))]
+    # the 3D workload of the metric beside the 2D one: FP64, BF16 and FP32 at 64 vectors
+    if args.config == "c2_2d_1m" and not args.no_variants and not args.no_3d:
+        c3 = h2gen.CONFIGS["c3_3d_512k"]
+        work.append(run_workload("c3_3d_512k", [(64, "fp64")] + [(64, p) for p in c3["precisions"]], args, torch))
 
+    name, buf, st, rows, results = work[0]
     r = results[(nv, "fp64")]
     alg = r["alg"]
     gflops = alg["flops"] / (r["t_ms"] * 1e-3) / 1e9
@@ -525,54 +547,139 @@ def main():
     else:
         achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "peak_measured_copy": round(copy_gbs, 1),
+                    "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
     roofline.update({"traffic": measured_traffic(args.config, nv, dom),
                      "kernel": f"{kname} ({dom} rows)",
                      "bytes_per_launch": dom_bytes, "flops_per_launch": dom_flops,
                      "ms_per_launch": round(dom_ms, 4)})
     path_gbs = alg["bytes"] / (r["t_ms"] * 1e-3) / 1e9
-    workloads = {
-        "c1_2d_4096": "2D N=4096 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 4x4 (k=16), eta=0.7",
-        "c2_2d_1m": "2D N=2^20 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 6x6 (k=36), eta=0.7",
-        "c3_3d_512k": "3D N=2^19 uniform [0,1]^3, leaf 64, 1/(4 pi r) zero diagonal, Chebyshev 4x4x4 (k=64), eta=0.7",
-    }
+    if not args.no_cpu:
+        cpu = cpu_leg(work, nv)
     out = {
         "metric": "H2 matvec Gflop/s", "value": round(gflops, 2), "unit": "Gflop/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["t_ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {workloads.get(args.config, '')}, nv={nv}, op N, alpha 1, beta 0",
+        "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, '')}, nv={nv}, op N, alpha 1, beta 0",
                    "n": st["n"], "nv": nv, "coupling_blocks": st["ncoupling"], "dense_blocks": st["ndense"],
                    "csp": st["csp"]},
         "roofline": roofline,
+        "error": {"rel_err_vs_oracle": r.get("rel_err"), "max_err_over_B": r.get("err_over_B"),
+                  "rows_checked": int(rows.size), "bar": "1e-12 (relative and per element over B)"},
         "path": {"gb_per_s": round(path_gbs, 1), "hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
                  "roofline": path_roofline(st, nv, "fp64", r["t_ms"]),
                  "alg_bytes": alg["bytes"], "alg_flops": alg["flops"], "phases_ms": r["prof"]},
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4),
                        "samples": int(r.get("lat_samples", len(r["per_call"]))),
-                       "launches_per_product": launches_per_product(g) if nv <= 4 else None},
-        "variants": [{"nv": v, "precision": prec, "ms": round(res["t_ms"], 4),
-                      "gflops": round(res["alg"]["flops"] / (res["t_ms"] * 1e-3) / 1e9, 2),
-                      "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
-                      "rel_err_vs_fp64": res.get("rel_err_vs_fp64"), "p99_ms": round(res["p99"], 4),
-                      "path_roofline": path_roofline(st, v, prec, res["t_ms"]),
-                      "phases_ms": res["prof"]}
-                     for (v, prec), res in results.items() if (v, prec) != (nv, "fp64")],
+                       "launches_per_product": r.get("launches")},
+        "hbm_copy_measured_gbs": round(copy_gbs, 1),
+        "variants": [variant_record(wname, wst, v, prec, res)
+                     for wname, _, wst, _, wres in work for (v, prec), res in wres.items()
+                     if (wname, v, prec) != (args.config, nv, "fp64")],
     }
     if not args.no_cpu:
-        Xh = h2gen.vectors(g.n, 1, cfg["seed_vec"])
-        g.close()
-        t_cpu, reps, thr, t_one = cpu_baseline(buf.array, Xh)
-        alg1 = algorithmic(st, 1)
-        out["cpu_baseline"] = {"value": round(alg1["flops"] / t_cpu / 1e9, 3), "unit": "Gflop/s", "cores": thr,
-                               "kind": "oracle",
-                               "sample": f"{reps} whole product(s) of the same operator at nv=1, "
-                                         f"{t_cpu:.2f} s each",
-                               "cpu": cpu_model(),
-                               "single_thread_value": (round(alg1["flops"] / t_one / 1e9, 3)
-                                                       if t_one else None)}
-    else:
-        g.close()
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+WORKLOADS = {
+    "c1_2d_4096": "2D N=4096 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 4x4 (k=16), eta=0.7",
+    "c2_2d_1m": "2D N=2^20 uniform [0,1]^2, leaf 64, exp(-r/0.1), Chebyshev 6x6 (k=36), eta=0.7",
+    "c3_3d_512k": "3D N=2^19 uniform [0,1]^3, leaf 64, 1/(4 pi r) zero diagonal, Chebyshev 4x4x4 (k=64), eta=0.7",
+}
+
+
+def run_workload(name, runs, args, torch, latency_for=None):
+    """Build and load one workload's operator, time each (nv, precision) run,
+    and keep each result's sampled output rows for the oracle check."""
+    import h2gen
+    from paper_2109_05451_amd import H2Operator
+    cfg = h2gen.CONFIGS[name]
+    t0 = time.perf_counter()
+    buf = h2gen.build_config(name)
+    print(f"# built {name}: {buf.nbytes / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    g = H2Operator(buf.array, device=0)
+    st = g.stats()
+    print(f"# loaded in {time.perf_counter() - t0:.1f} s; stats {st}", file=sys.stderr, flush=True)
+    rows = sample_rows(g.n, cfg["seed_vec"])
+    rows_dev = torch.from_numpy(rows).cuda()
+    results = {}
+    for v, prec in runs:
+        Xh = h2gen.vectors(g.n, v, cfg["seed_vec"])
+        X = torch.from_numpy(np.asfortranarray(Xh)).cuda()
+        Y = torch.empty((v, g.n), dtype=torch.float64, device="cuda").t()
+        wall, per_call, prof = time_gpu(g, X, Y, v, args.steps, args.warmup, torch, prec)
+        alg = algorithmic(st, v)
+        srt = np.sort(per_call)
+        trimmed = srt[1:-1] if srt.size > 2 else srt  # the paper drops the fastest and the slowest
+        t_ms = float(np.mean(trimmed))
+        phases = {k[3:]: prof[k] / prof["calls"] for k in prof if k.startswith("ms_")}
+        res = dict(wall=wall, per_call=per_call, t_ms=t_ms, prof=phases, alg=alg,
+                   p50=float(np.percentile(per_call, 50)), p99=float(np.percentile(per_call, 99)))
+        if (v, prec) == latency_for and args.latency_calls > 0:
+            lat = latency_gpu(g, X, Y, v, args.latency_calls, torch)
+            res.update(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)), lat_samples=lat.size)
+        if v <= 4 and prec == "fp64":
+            res["launches"] = launches_per_product(g)
+        res["got_rows"] = Y.index_select(0, rows_dev).cpu().numpy()
+        res["finite"] = bool(torch.isfinite(Y).all().item())
+        results[(v, prec)] = res
+        print(f"# {name} nv={v} {prec}: {t_ms:.3f} ms/call, phases {phases}", file=sys.stderr, flush=True)
+        del X, Y
+    g.close()
+    torch.cuda.empty_cache()
+    return name, buf, st, rows, results
+
+
+def variant_record(name, st, v, prec, res) -> dict:
+    return {"workload": name, "nv": v, "precision": prec, "ms": round(res["t_ms"], 4),
+            "gflops": round(res["alg"]["flops"] / (res["t_ms"] * 1e-3) / 1e9, 2),
+            "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
+            "rel_err_vs_oracle": res.get("rel_err"), "max_err_over_B": res.get("err_over_B"),
+            "finite": res["finite"], "p99_ms": round(res["p99"], 4),
+            "roofline": coupling_roofline(st, v, prec, res["prof"]["coupling"]),
+            "path_roofline": path_roofline(st, v, prec, res["t_ms"]),
+            "phases_ms": res["prof"]}
+
+
+def cpu_leg(work, nv) -> dict:
+    """The CPU leg: the oracle timed on the headline operator (whole products
+    at nv = 1 on the host's cores), then the oracle's values of the sampled
+    output rows of every GPU result (exact rows at any size: the whole column
+    upsweep, then only the sampled leaves' root paths), which give each
+    result's error against the FP64 oracle."""
+    import h2gen
+    import oracle
+    name, buf, st, rows, results = work[0]
+    cfg = h2gen.CONFIGS[name]
+    t_cpu, reps, thr, t_one = cpu_baseline(buf.array, h2gen.vectors(st["n"], 1, cfg["seed_vec"]))
+    alg1 = algorithmic(st, 1)
+    t0 = time.perf_counter()
+    for wname, wbuf, wst, wrows, wres in work:
+        wcfg = h2gen.CONFIGS[wname]
+        o = oracle.Oracle(wbuf.array)
+        for v in sorted({v for v, _ in wres}):
+            Xh = h2gen.vectors(wst["n"], v, wcfg["seed_vec"])
+            want = o.gemv_rows(wrows, Xh)
+            B = o.gemv_rows(wrows, Xh, absval=True)
+            for (vv, prec), res in wres.items():
+                if vv != v:
+                    continue
+                d = res["got_rows"] - want
+                res["rel_err"] = float(np.linalg.norm(d) / np.linalg.norm(want))
+                res["err_over_B"] = float(np.max(np.abs(d) / np.where(B > 0, B, 1.0)))
+        o.close()
+        print(f"# oracle rows of {wname} done", file=sys.stderr, flush=True)
+    t_rows = time.perf_counter() - t0
+    return {"value": round(alg1["flops"] / t_cpu / 1e9, 3), "unit": "Gflop/s", "cores": thr, "kind": "oracle",
+            "sample": f"{reps} whole product(s) of the {name} operator at nv=1, {t_cpu:.2f} s each; the "
+                      f"oracle then computed {work[0][3].size} sampled output rows of every GPU result "
+                      f"({t_rows:.1f} s) for the errors",
+            "cpu": cpu_model(),
+            "single_thread_value": (round(alg1["flops"] / t_one / 1e9, 3) if t_one else None)}
 
 
 if __name__ == "__main__":

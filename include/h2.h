@@ -76,7 +76,25 @@ typedef struct {
   int64_t device_bytes;   /* device memory held by the handle now */
   int64_t max_rank;       /* largest rank of any level */
   int64_t max_leaf;       /* largest leaf size */
+  /* Algorithmic work of one FP64 product with nv vectors (every stored entry
+   * read once, the vector trees x^ and y^ written once and read once):
+   *   flops = alg_flops_per_vector * nv + 2 n nv if beta != 0
+   *   bytes = alg_bytes_matrix + alg_bytes_per_vector * nv + 8 n nv if beta != 0 */
+  double alg_flops_per_vector;  /* 2 * (all stored entries) + n (the alpha scaling) */
+  double alg_bytes_matrix;      /* 8 * (all stored entries) */
+  double alg_bytes_per_vector;  /* 8 * (2 n + 4 tree_rows): X read, Y written, x^ and y^ */
 } h2_stats_t;
+
+/* Structure of one level of the cluster tree (root = level 0). */
+typedef struct {
+  int64_t nodes;            /* nodes of the level */
+  int64_t krow, kcol;       /* ranks of the row and column bases on the level */
+  int64_t coupling_blocks;  /* coupling blocks S_ts with t, s on the level */
+  int64_t csp;              /* largest number of coupling blocks in a block row or column of the level */
+  int64_t entries_S;        /* stored entries of those blocks */
+  int64_t entries_E;        /* stored entries of the level's transfers E (0 on the root level) */
+  int64_t entries_F;        /* the same for F (counted even when F = E) */
+} h2_level_stats_t;
 
 /* Per-phase GPU time accumulated over the h2_gemv calls made while profiling
  * was on (h2_profile), measured with HIP events recorded on the stream each
@@ -152,12 +170,14 @@ int h2_prepare(h2_handle h, int prec);
 int h2_reserve(h2_handle h, int64_t nv_max);
 
 /* Autotune the multi-vector (MFMA) path of op 'N' for `nv` vectors in
- * precision `prec`: for every launch of the product, each candidate chunk
- * width (32 or 64 columns; BF16 has 64 only) and grid (one workgroup per
+ * precision `prec`: for every launch of the product, each candidate kernel
+ * form (the h2_tune_set codes; BF16 has one form) and grid (one workgroup per
  * row, or a persistent grid of 1024, 2048 or 4096 workgroups) is timed with
  * HIP events on `stream` (three runs, the first discarded) on zeroed
  * workspace buffers, and the fastest is kept for later calls in that
- * precision (the dense rows, always FP64, keep theirs in the FP64 entry).
+ * precision (the dense rows, always FP64, keep theirs in the FP64 entry);
+ * then the fused sweeps are timed against the tuned per-level sweeps and the
+ * faster form is kept (h2_set_sweeps).
  * Results do not depend on the choice: every candidate sums each output in
  * the same order, so they are bitwise identical.  No-op for nv <= 4 outside
  * BF16 (the streaming kernel has nothing to tune).  Synchronous; must not run concurrently with other calls on the
@@ -218,11 +238,21 @@ int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
  * columns (loads one or two chunks ahead) compiled for four workgroups per
  * CU, 7 or 8 the same with 8 columns and five workgroups per CU (0-8 take
  * passes of 64 vectors, 1-8 rows of at most 64 outputs; other launches use
- * 64 columns); grid = workgroups (0 = one per
+ * 64 columns), 9 for one wave per row with no LDS staging (rows of at most
+ * 64 outputs, any pass width); grid = workgroups (0 = one per
  * row); xcd != 0 for XCD-aware row ranges; tree_order != 0 for tree-ordered
  * coupling and dense rows.  Results do not change (same summation order).  For
  * reproducible timing and for tests.  Errors: H2_EINVAL. */
 int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_order);
+
+/* How the multi-vector path (op 'N', 64-vector passes or fewer, FP64 and
+ * FP32) runs the upsweep, the downsweep and the leaf expansion: fused != 0
+ * in a few launches in which each workgroup runs several levels of one
+ * subtree (the default when every row has at most 64 outputs), 0 one launch
+ * per level.  Results are bitwise the same; h2_tune keeps the faster.
+ * Errors: H2_EINVAL (null handle, precision other than FP64 or FP32),
+ * H2_EUNSUPPORTED (fused asked for, but the operator has longer rows). */
+int h2_set_sweeps(h2_handle h, int prec, int fused);
 
 /* A text description of the op-'N' launch plan and its tuned parameters
  * (row order per precision; per launch: rows, chunk width, grid, XCD mapping
@@ -232,6 +262,10 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed);
 
 /* Fill *st with the operator's structure and stored-entry counts. */
 int h2_stats(h2_handle h, h2_stats_t* st);
+
+/* Fill *out with the structure of level `level` (0 <= level <= depth).
+ * Errors: H2_EINVAL (null arguments, level out of range). */
+int h2_level_stats(h2_handle h, int64_t level, h2_level_stats_t* out);
 
 /* Matrix order n of a loaded operator, or -1 for a NULL handle. */
 int64_t h2_n(h2_handle h);
@@ -287,8 +321,9 @@ int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, in
 int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream);
 
 /* Autotuner: for every merged launch, time each candidate shape (columns
- * staged per LDS chunk: 32 or 64; workgroups: one per row or a persistent
- * grid of 1024, 2048 or 4096) on these items and keep the fastest.
+ * staged per LDS chunk: 32 or 64, or one wave per row with no LDS staging;
+ * workgroups: one per row (four rows for the wave form) or a persistent grid
+ * of 1024, 2048 or 4096) on these items and keep the fastest.
  * Synchronous; the workspace content afterwards is unspecified. */
 int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream);
 
@@ -313,7 +348,11 @@ int h2_batch_free(h2_batch b);
  * vectors), so requests arriving while others run join the next call
  * (continuous batching) and calls on different slots overlap on the GPU.
  * Requests hold device pointers (column-major n x nv, leading dimension n,
- * original point order) that must stay valid until the request completes. */
+ * original point order) that must stay valid until the request completes.
+ * Nothing in the scheduler allocates device memory or synchronizes the
+ * device: the budget is one region allocated at creation, and a precision
+ * other than FP64 must have been prepared on an operator (h2_prepare) before
+ * requests use it. */
 typedef struct h2_server_s* h2_server;
 
 typedef struct {
@@ -321,22 +360,37 @@ typedef struct {
   int64_t calls;                  /* fused products issued */
   int64_t vectors;                /* vectors served */
   int64_t max_inflight_calls;     /* largest number of calls running at once */
-  int64_t slots;                  /* slots the budget allowed */
+  int64_t slots;                  /* slots */
   int64_t budget_bytes;           /* device memory for call buffers */
+  int64_t hbm_free_at_create;     /* free HBM (hipMemGetInfo) when the budget was taken */
+  double alg_bytes;               /* algorithmic bytes of the calls issued: low-rank data at the
+                                     call's precision, dense blocks and vectors in FP64 */
+  double alg_flops;               /* algorithmic flops of the calls issued (2 per stored entry
+                                     and vector, plus n per vector) */
 } h2_server_stats_t;
 
 /* Create a server over `nops` loaded handles (all on one device; the server
  * does not own them).  `slots` concurrent calls at most, each slot with a
  * workspace sized for the largest operator; `budget_bytes` of device memory
- * for the calls' fused input/output buffers (admission waits when it is
- * exhausted); `max_fuse_nv` (1..64) vectors per fused call.
+ * for the calls' fused input/output buffers, taken from the HBM that is free
+ * after the slots' workspaces (hipMemGetInfo): budget_bytes <= 0 takes a
+ * quarter of it, and a budget above 90% of it is refused (H2_ENOMEM).
+ * Admission waits while the budget is exhausted.  `max_fuse_nv` (1..64)
+ * vectors per fused call.
  * Errors: H2_EINVAL, H2_ENOMEM, H2_EHIP. */
 int h2_server_create(const h2_handle* ops, int64_t nops, int64_t slots, int64_t budget_bytes,
                      int64_t max_fuse_nv, h2_server* out);
 
 /* Queue Y <- op(A_op) X (op 'N', alpha 1, beta 0) in precision `prec`;
- * nv <= max_fuse_nv.  Returns at once with the request id in *id. */
-int h2_server_submit(h2_server s, int64_t op, int prec, int64_t nv, const double* X, double* Y, int64_t* id);
+ * nv <= max_fuse_nv.  `stream` (a hipStream_t, NULL = the null stream) is
+ * the stream whose work produces X: an event recorded on it now orders the
+ * server's read of X after that work, so the caller need not synchronize.
+ * Y is written by the server's own streams; read it after h2_server_wait.
+ * Returns at once with the request id in *id.
+ * Errors: H2_EINVAL (bad arguments, a request larger than the budget, a
+ * precision not prepared on the operator), H2_EHIP. */
+int h2_server_submit(h2_server s, int64_t op, int prec, int64_t nv, const double* X, double* Y, void* stream,
+                     int64_t* id);
 
 /* Block until request `id` has completed; *latency_ms (optional) receives
  * the time from submission to completion as seen by the scheduler. */

@@ -20,8 +20,8 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_prepare", "h2_reserve", "h2_tune",
-           "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set",
-           "h2_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
+           "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set", "h2_set_sweeps",
+           "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
 
@@ -32,7 +32,16 @@ class H2Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "depth", "nnodes", "nleaves", "ncoupling", "ndense", "csp", "csp_dense",
         "entries_U", "entries_V", "entries_E", "entries_F", "entries_S", "entries_D",
-        "tree_rows", "shared_basis", "device_bytes", "max_rank", "max_leaf")]
+        "tree_rows", "shared_basis", "device_bytes", "max_rank", "max_leaf")] + [
+        (name, ctypes.c_double) for name in ("alg_flops_per_vector", "alg_bytes_matrix", "alg_bytes_per_vector")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class H2LevelStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "nodes", "krow", "kcol", "coupling_blocks", "csp", "entries_S", "entries_E", "entries_F")]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -64,10 +73,11 @@ class H2BatchItem(ctypes.Structure):
 
 class H2ServerStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
-        "submitted", "completed", "calls", "vectors", "max_inflight_calls", "slots", "budget_bytes")]
+        "submitted", "completed", "calls", "vectors", "max_inflight_calls", "slots", "budget_bytes",
+        "hbm_free_at_create")] + [("alg_bytes", ctypes.c_double), ("alg_flops", ctypes.c_double)]
 
     def as_dict(self):
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class H2Error(RuntimeError):
@@ -114,8 +124,12 @@ def load_library(path: str = LIB_PATH):
     lib.h2_plan_info.restype = ci
     lib.h2_tune_set.argtypes = [vp, ci, ci, i64, ci, ci]
     lib.h2_tune_set.restype = ci
+    lib.h2_set_sweeps.argtypes = [vp, ci, ci]
+    lib.h2_set_sweeps.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
     lib.h2_stats.restype = ci
+    lib.h2_level_stats.argtypes = [vp, i64, ctypes.POINTER(H2LevelStats)]
+    lib.h2_level_stats.restype = ci
     lib.h2_n.argtypes = [vp]
     lib.h2_n.restype = i64
     lib.h2_profile.argtypes = [vp, ci]
@@ -138,7 +152,7 @@ def load_library(path: str = LIB_PATH):
     lib.h2_batch_free.restype = ci
     lib.h2_server_create.argtypes = [ctypes.POINTER(vp), i64, i64, i64, i64, ctypes.POINTER(vp)]
     lib.h2_server_create.restype = ci
-    lib.h2_server_submit.argtypes = [vp, i64, ci, i64, vp, vp, ctypes.POINTER(i64)]
+    lib.h2_server_submit.argtypes = [vp, i64, ci, i64, vp, vp, vp, ctypes.POINTER(i64)]
     lib.h2_server_submit.restype = ci
     lib.h2_server_wait.argtypes = [vp, i64, ctypes.POINTER(dbl)]
     lib.h2_server_wait.restype = ci
@@ -221,6 +235,10 @@ class H2Operator:
         _check(load_library().h2_tune_set(self._h, PRECISIONS[precision], kc, grid, 1 if xcd else 0,
                                           int(tree_order)))
 
+    def set_sweeps(self, precision: str = "fp64", fused: bool = True):
+        """Fused subtree sweeps or one launch per level (see h2_set_sweeps)."""
+        _check(load_library().h2_set_sweeps(self._h, PRECISIONS[precision], 1 if fused else 0))
+
     def plan_info(self) -> str:
         """Text description of the launch plan and its tuned parameters."""
         lib = load_library()
@@ -242,6 +260,15 @@ class H2Operator:
         st = H2Stats()
         _check(load_library().h2_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
+
+    def level_stats(self) -> list:
+        """Per-level structure, root first (see h2_level_stats)."""
+        out = []
+        for level in range(self.stats()["depth"] + 1):
+            ls = H2LevelStats()
+            _check(load_library().h2_level_stats(self._h, level, ctypes.byref(ls)))
+            out.append(ls.as_dict())
+        return out
 
     def reserve(self, nv_max: int):
         _check(load_library().h2_reserve(self._h, nv_max))
@@ -289,17 +316,24 @@ class H2Operator:
                 t = t.t().contiguous().t()
             return t
 
-        X = colmajor(X)
-        nv = X.shape[1]
-        if Y is None:
-            Y = torch.empty((nv, self.n), dtype=torch.float64, device=dev).t()
-            beta = 0.0
-        else:
-            Y = colmajor(Y)
-        ldx = X.stride(1) if nv > 1 else self.n
-        ldy = Y.stride(1) if nv > 1 else self.n
         s = stream if stream is not None else torch.cuda.current_stream(dev)
-        self.gemv_raw(op, alpha, X.data_ptr(), ldx, nv, beta, Y.data_ptr(), ldy, s.cuda_stream, precision)
+        with torch.cuda.stream(s):
+            X = colmajor(X)
+            nv = X.shape[1]
+            Y_in = Y
+            if Y is None:
+                Y = torch.empty((nv, self.n), dtype=torch.float64, device=dev).t()
+                beta = 0.0
+            else:
+                Y = colmajor(Y)
+            ldx = X.stride(1) if nv > 1 else self.n
+            ldy = Y.stride(1) if nv > 1 else self.n
+            self.gemv_raw(op, alpha, X.data_ptr(), ldx, nv, beta, Y.data_ptr(), ldy, s.cuda_stream, precision)
+            if Y_in is not None and Y.data_ptr() != Y_in.data_ptr():
+                # Y was converted to a column-major FP64 device copy: write
+                # the result back into the caller's tensor (in place)
+                Y_in.copy_(Y.reshape(Y_in.shape))
+                return Y_in
         return Y
 
 
@@ -375,9 +409,12 @@ class H2Server:
     """Serving loop over resident operators (continuous batching in C++).
 
     ``submit(op, X, precision)`` queues Y = A_op X for a device tensor X
-    (n x nv, column-major, leading dimension n) and returns a request id; the
-    output tensor is allocated here and returned by ``wait(id)`` together with
-    the request's latency in ms."""
+    (n x nv; any layout: a column-major copy is made on the current stream)
+    and returns a request id.  The server reads X after the work queued on
+    the current stream so far, so X may still be in production.  The output
+    tensor is allocated here and returned by ``wait(id)`` together with the
+    request's latency in ms.  ``budget_bytes`` <= 0 takes a quarter of the
+    free HBM."""
 
     def __init__(self, ops, slots: int = 4, budget_bytes: int = 1 << 30, max_fuse_nv: int = 64):
         lib = load_library()
@@ -392,13 +429,15 @@ class H2Server:
         import torch
         n = self._ops[op].n
         X = X.reshape(n, -1) if X.dim() == 1 else X
+        X = X.to(dtype=torch.float64)
         if X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) != n):
             X = X.t().contiguous().t()
         nv = X.shape[1]
         Y = torch.empty((nv, n), dtype=torch.float64, device=X.device).t()
         rid = ctypes.c_int64()
+        stream = torch.cuda.current_stream(X.device).cuda_stream
         _check(load_library().h2_server_submit(self._h, op, PRECISIONS[precision], nv, X.data_ptr(), Y.data_ptr(),
-                                               ctypes.byref(rid)))
+                                               stream or None, ctypes.byref(rid)))
         self._live[rid.value] = (X, Y)
         return rid.value
 

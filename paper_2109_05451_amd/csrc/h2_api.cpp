@@ -6,6 +6,7 @@
 #include <array>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -139,12 +140,107 @@ void free_device(h2_op_s* h) {
   F(h->d_mat16); F(h->d_trans16);
   F(h->rt.d_rows); F(h->rt.d_colend); F(h->rt.d_in_off);
   F(h->wide.d_rows); F(h->wide.d_colend); F(h->wide.d_in_off);
-  F(h->gt.d_rows); F(h->gt.d_data); F(h->gt.d_mr); F(h->gt.d_in_off);
+  F(h->gt.d_rows); F(h->gt.d_data); F(h->gt.d_mr); F(h->gt.d_in_off); F(h->d_tree_ranges);
   for (auto& set : h->ev_pool)
     for (hipEvent_t e : set)
       if (e) (void)hipEventDestroy(e);
   h->ev_pool.clear();
   ws_destroy(&h->ws);
+}
+
+// Fused sweeps of the op-'N' multi-vector path.  Level boundaries
+// 0 = b_0 < ... < b_k = q, the last interval four levels deep (its subtree
+// roots are the nodes of level q - 4: 1024 of them for 2^14 leaves) and the
+// others five.  Upsweep group i (i = k .. 1, run in that order) has a
+// workgroup per node of level b_(i-1) and runs, bottom-up, the leaf products
+// (last interval only) and the transfer rows of the parents on levels
+// b_i - 1 .. b_(i-1); downsweep group i (i = 1 .. k) runs, top-down, the rows
+// of the children on levels b_(i-1) + 1 .. b_i and, in the last interval,
+// the leaf expansion.  A workgroup's rows on a level are the node range its
+// subtree covers there.  Leaves true when every launch of the plan is one
+// narrow row list in node order and every row has at most 64 outputs.
+bool build_tree_groups(h2_op_s* h, const Parsed& P, const OpLayout& lay, std::vector<int2>* ranges) {
+  const int64_t q = P.q;
+  const int64_t* lp = P.level_ptr;
+  const Plan& plan = h->planN;
+  if ((int64_t)plan.up.size() != q + 1 || (int64_t)plan.down.size() != q) return false;
+  auto narrow_of = [](const Launch& L, int64_t rows) { return L.kind == KIND_STREAM && L.row_count == rows; };
+  if (!narrow_of(plan.up[0], P.nleaves) || !narrow_of(plan.out, P.nleaves)) return false;
+  for (int64_t l = 1; l <= q; ++l)
+    if (!narrow_of(plan.up[q - l + 1], lp[l] - lp[l - 1]) || !narrow_of(plan.down[l - 1], lp[l + 1] - lp[l]))
+      return false;
+  std::vector<int64_t> bnd;  // increasing boundaries
+  {
+    int64_t b = q;
+    bnd.push_back(b);
+    if (q > 0) {
+      b = std::max<int64_t>(0, q - 4);
+      bnd.push_back(b);
+      while (b > 0) {
+        b = std::max<int64_t>(0, b - 5);
+        bnd.push_back(b);
+      }
+    } else {
+      bnd.push_back(0);
+    }
+    std::reverse(bnd.begin(), bnd.end());
+  }
+  const int64_t k = (int64_t)bnd.size() - 1;
+  // descendants of node r on level l (l >= level of r): one node range
+  auto desc = [&](int64_t r, int64_t lr, int64_t l) {
+    int64_t lo = r, hi = r + 1;
+    for (int64_t x = lr; x < l; ++x) {
+      lo = lay.cbeg[lo];
+      hi = lay.cbeg[hi];
+    }
+    return std::make_pair(lo, hi);
+  };
+  // one level entry of a group: the rows of launch L for the nodes [lo, hi)
+  // of a level whose first node is `first`
+  struct Entry { const Launch* L; int64_t level; int64_t first; int in, out, mode; };
+  auto add_group = [&](std::vector<TreeGroup>& dst, int64_t root_level, const std::vector<Entry>& ent, bool up) {
+    TreeGroup G;
+    G.lv.nlev = (int)ent.size();
+    G.nwg = lp[root_level + 1] - lp[root_level];
+    G.range_off = (int64_t)ranges->size();
+    G.trans_data = up;
+    for (size_t j = 0; j < ent.size(); ++j) {
+      G.lv.in[j] = ent[j].in;
+      G.lv.out[j] = ent[j].out;
+      G.lv.mode[j] = ent[j].mode;
+      G.max_rows = std::max(G.max_rows, ent[j].L->max_rows);
+    }
+    for (int64_t r = lp[root_level]; r < lp[root_level + 1]; ++r)
+      for (const Entry& e : ent) {
+        const auto d = desc(r, root_level, e.level);
+        const int64_t b = e.L->row_begin + (d.first - e.first), c = e.L->row_begin + (d.second - e.first);
+        ranges->push_back(int2{(int)b, (int)c});
+      }
+    dst.push_back(G);
+  };
+  if ((int64_t)h->rt.rows.size() >= (int64_t)1 << 31) return false;
+  for (int64_t i = k; i >= 1; --i) {
+    std::vector<Entry> ent;
+    if (i == k) ent.push_back({&plan.up[0], q, lp[q], BUF_XT, BUF_XH, MODE_STORE});
+    for (int64_t l = bnd[i]; l > bnd[i - 1]; --l)  // parents on level l - 1
+      ent.push_back({&plan.up[q - l + 1], l - 1, lp[l - 1], BUF_XH, BUF_XH, MODE_STORE});
+    if (ent.empty()) continue;
+    if ((int)ent.size() > kMaxTreeLevels) return false;
+    add_group(h->tree_up, bnd[i - 1], ent, true);
+  }
+  for (int64_t i = 1; i <= k; ++i) {
+    std::vector<Entry> ent;
+    for (int64_t l = bnd[i - 1] + 1; l <= bnd[i]; ++l)
+      ent.push_back({&plan.down[l - 1], l, lp[l], BUF_YH, BUF_YH, MODE_ACCUM});
+    if (i == k) ent.push_back({&plan.out, q, lp[q], BUF_YH, 3, MODE_STORE});
+    if (ent.empty()) continue;
+    if ((int)ent.size() > kMaxTreeLevels) return false;
+    add_group(h->tree_down, bnd[i - 1], ent, false);
+  }
+  for (const auto* v : {&h->tree_up, &h->tree_down})
+    for (const TreeGroup& G : *v)
+      if (G.max_rows > 64) return false;
+  return true;
 }
 
 // Build plans and upload; the handle's device is current.
@@ -226,6 +322,13 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
     }
     plan.out = outl[0];
   }
+  std::vector<int2> tree_ranges;
+  h->tree_ok = build_tree_groups(h, P, lay, &tree_ranges);
+  if (!h->tree_ok) {
+    h->tree_up.clear();
+    h->tree_down.clear();
+    tree_ranges.clear();
+  }
   // ---- plan for op 'T' (A^T = D^T + V S^T U^T): upsweep with U, E; coupling
   // and dense blocks read transposed; downsweep with V, F
   {
@@ -291,15 +394,27 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
 
   // ---- stats
   int64_t csp = 0, csp_dense = 0;
+  h->level_stats.assign(q + 1, h2_level_stats_t{});
   for (int64_t l = 0; l <= q; ++l) {
     const int64_t* rp = P.s_rowptr + P.rp_base[l];
     const int64_t nl = lp[l + 1] - lp[l];
+    int64_t lcsp = 0;
     std::vector<int64_t> colcnt(nl, 0);
     for (int64_t t = 0; t < nl; ++t) {
-      csp = std::max(csp, rp[t + 1] - rp[t]);
+      lcsp = std::max(lcsp, rp[t + 1] - rp[t]);
       for (int64_t b = rp[t]; b < rp[t + 1]; ++b) ++colcnt[P.s_col[P.blk_base[l] + b]];
     }
-    for (int64_t c : colcnt) csp = std::max(csp, c);
+    for (int64_t c : colcnt) lcsp = std::max(lcsp, c);
+    csp = std::max(csp, lcsp);
+    h2_level_stats_t& ls = h->level_stats[l];
+    ls.nodes = nl;
+    ls.krow = P.krow[l];
+    ls.kcol = P.kcol[l];
+    ls.coupling_blocks = P.blk_base[l + 1] - P.blk_base[l];
+    ls.csp = lcsp;
+    ls.entries_S = P.sdat[l + 1] - P.sdat[l];
+    ls.entries_E = l > 0 ? nl * P.krow[l] * P.krow[l - 1] : 0;
+    ls.entries_F = l > 0 ? nl * P.kcol[l] * P.kcol[l - 1] : 0;
   }
   {
     std::vector<int64_t> colcnt(P.nleaves, 0);
@@ -320,6 +435,13 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
   st.shared_basis = h->shared ? 1 : 0;
   for (int64_t l = 0; l <= q; ++l) st.max_rank = std::max(st.max_rank, h->lv[l].kmax);
   for (int64_t t = P.leaf0; t < P.nnodes; ++t) st.max_leaf = std::max<int64_t>(st.max_leaf, msz(t));
+  {
+    const double entries = (double)(st.entries_U + st.entries_V + st.entries_E + st.entries_F + st.entries_S +
+                                    st.entries_D);
+    st.alg_flops_per_vector = 2.0 * entries + (double)n;
+    st.alg_bytes_matrix = 8.0 * entries;
+    st.alg_bytes_per_vector = 8.0 * (2.0 * (double)n + 4.0 * (double)st.tree_rows);
+  }
 
   // ---- upload
   const int64_t mat_bytes = P.off_end - P.off_U;
@@ -353,7 +475,7 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
       (rc = upload(h->wide.colend, &h->wide.d_colend, &ib)) ||
       (rc = upload(h->wide.in_off, &h->wide.d_in_off, &ib)) || (rc = upload(h->gt.rows, &h->gt.d_rows, &ib)) ||
       (rc = upload(h->gt.data, &h->gt.d_data, &ib)) || (rc = upload(h->gt.mr, &h->gt.d_mr, &ib)) ||
-      (rc = upload(h->gt.in_off, &h->gt.d_in_off, &ib)))
+      (rc = upload(h->gt.in_off, &h->gt.d_in_off, &ib)) || (rc = upload(tree_ranges, &h->d_tree_ranges, &ib)))
     return rc;
   h->index_bytes = ib;
   h->stats.device_bytes = mat_bytes + ntrans * (int64_t)sizeof(double) + ib;
@@ -443,7 +565,13 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   double* out = bufs[mode_override >= 0 ? BUF_ZN : L.out];
   const int mode = mode_override >= 0 ? mode_override : L.mode;
   hipError_t e = hipSuccess;
-  if (nvp > 0) {
+  if (nvp > 0 && L.kcp[lowp ? H2_PREC_FP32 : H2_PREC_FP64] == kWaveRows && L.max_rows <= 64) {
+    const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
+    e = lowp ? launch_wave_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.gridp[pi])
+             : launch_wave_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.gridp[pi]);
+  } else if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
     e = lowp ? launch_rows_mfma<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
@@ -474,6 +602,7 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
 }
 
 int prepare_f32(h2_op_s* h) {
+  std::lock_guard<std::mutex> lock(h->prep_mu);  // a concurrent call may be preparing it
   if (h->d_mat32 || h->n_lowrank + h->n_trans == 0) return H2_OK;
   float *m32 = nullptr, *t32 = nullptr;
   hipError_t e;
@@ -494,6 +623,7 @@ int prepare_f32(h2_op_s* h) {
 }
 
 int prepare_bf16(h2_op_s* h) {
+  std::lock_guard<std::mutex> lock(h->prep_mu);
   if (h->d_mat16 || h->n_lowrank + h->n_trans == 0) return H2_OK;
   void *m16 = nullptr, *t16 = nullptr;
   hipError_t e;
@@ -515,6 +645,28 @@ int prepare_bf16(h2_op_s* h) {
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(BF16 copy)");
   h->stats.device_bytes += 2 * (h->n_lowrank + h->n_trans);
   return H2_OK;
+}
+
+// The fused sweep launches of one direction (multi-vector path, FP64/FP32).
+int run_tree(h2_op_s* h, const Workspace& w, const std::vector<TreeGroup>& groups, int nvp, int prec,
+             hipStream_t s) {
+  double* const bufs[4] = {w.xt, w.xh, w.yh, w.zx};
+  for (const TreeGroup& G : groups) {
+    const hipError_t e =
+        prec == H2_PREC_FP32
+            ? launch_tree<float>(h->d_tree_ranges + G.range_off, G.nwg, G.lv, h->rt.d_rows, h->rt.d_colend,
+                                 h->rt.d_in_off, G.trans_data ? h->d_trans32 : h->d_mat32, bufs, nvp, G.max_rows, s)
+            : launch_tree<double>(h->d_tree_ranges + G.range_off, G.nwg, G.lv, h->rt.d_rows, h->rt.d_colend,
+                                  h->rt.d_in_off, G.trans_data ? h->d_trans : h->d_mat, bufs, nvp, G.max_rows, s);
+    if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
+  }
+  return H2_OK;
+}
+
+// Whether a multi-vector pass runs the fused sweeps.
+bool use_tree(const h2_op_s* h, const Workspace& w, bool trans, int nvp, int prec) {
+  const int pidx = prec == H2_PREC_FP32 ? 1 : prec == H2_PREC_BF16 ? 2 : 0;
+  return nvp > 0 && !trans && prec != H2_PREC_BF16 && h->tree_ok && w.zx != nullptr && h->sweep_fused[pidx] != 0;
 }
 
 // One pass of the product: nv <= kPassVectors vectors on the streaming path
@@ -555,7 +707,10 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   STEP(mark(5, w.side));
   for (const Launch& L : dense1) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
   STEP(mark(9, w.side));
-  for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  const bool fused = use_tree(h, w, trans, nvp, prec);
+  if (fused) STEP(run_tree(h, w, h->tree_up, nvp, prec, s));
+  else
+    for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
   const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
   if (x32) HIP_TRY(launch_to_f32(w.xh, w.xh32, h->H * (int64_t)nvp, s), "x^ to FP32");
@@ -569,11 +724,17 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   for (const Launch& L : dense2) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
   STEP(mark(6, w.side));
   HIP_TRY(hipEventRecord(w.ev_join, w.side), "hipEventRecord(join)");
-  for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  // (the fused downsweep ends with the leaf expansion into w.zx, beside the dense rows)
+  if (fused) STEP(run_tree(h, w, h->tree_down, nvp, prec, s));
+  else
+    for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
   STEP(mark(4, s));
   HIP_TRY(hipStreamWaitEvent(s, w.ev_join, 0), "hipStreamWaitEvent(join)");
   STEP(mark(7, s));
-  if (nvp) {
+  if (fused) {
+    // Y = alpha (Z + U y^)[pinv] + beta Y
+    HIP_TRY(launch_permute_out_rm2(w.zn, w.zx, h->d_pinv, alpha, beta, Y, ldy, h->n, nv, nvp, s), "permute out");
+  } else if (nvp) {
     // Z += U y^ (into the dense partial), then Y = alpha Z[pinv] + beta Y
     STEP(run_launch(h, w, plan.out, nv, ep, s, nvp, MODE_ACCUM, prec));
     HIP_TRY(launch_permute_out_rm(w.zn, h->d_pinv, alpha, beta, Y, ldy, h->n, nv, nvp, s), "permute out");
@@ -589,6 +750,14 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
 
 int load_handle(const uint8_t* buf, int64_t len, int device, const double* d_dense, h2_handle* out) {
   return load_common(buf, len, device, out, d_dense);
+}
+
+bool prepared(h2_op_s* h, int prec) {
+  if (prec == H2_PREC_FP64) return true;
+  std::lock_guard<std::mutex> lock(h->prep_mu);
+  const bool empty = h->n_lowrank + h->n_trans == 0;
+  if (prec == H2_PREC_FP32) return empty || h->d_mat32 != nullptr;
+  return h->mfma_ok && (empty || h->d_mat16 != nullptr);
 }
 }  // namespace h2
 
@@ -643,7 +812,9 @@ namespace h2 {
 int64_t ws_bytes(int64_t n, int64_t H, int64_t cap) {
   return (int64_t)sizeof(double) *
              (2 * std::max<int64_t>(n, 1) + std::max<int64_t>(H, 8) + std::max<int64_t>(H, 1)) * cap +
-         (cap >= kPassVectorsMfma ? (int64_t)sizeof(float) * std::max<int64_t>(H, 1) * cap : 0);
+         (cap >= kPassVectorsMfma ? (int64_t)sizeof(float) * std::max<int64_t>(H, 1) * cap +
+                                        (int64_t)sizeof(double) * std::max<int64_t>(n, 1) * cap
+                                  : 0);
 }
 
 int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
@@ -660,6 +831,8 @@ int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
       (e = hipMalloc(reinterpret_cast<void**>(&w->zn), sizeof(double) * nn * cap)) != hipSuccess ||
       (cap >= kPassVectorsMfma &&
        (e = hipMalloc(reinterpret_cast<void**>(&w->xh32), sizeof(float) * Hs * cap)) != hipSuccess) ||
+      (cap >= kPassVectorsMfma &&
+       (e = hipMalloc(reinterpret_cast<void**>(&w->zx), sizeof(double) * nn * cap)) != hipSuccess) ||
       (e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming)) != hipSuccess ||
@@ -675,6 +848,7 @@ void ws_destroy(Workspace* w) {
   for (double* p : {w->xt, w->xh, w->yh, w->zn})
     if (p) (void)hipFree(p);
   if (w->xh32) (void)hipFree(w->xh32);
+  if (w->zx) (void)hipFree(w->zx);
   if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
   if (w->ev_join) (void)hipEventDestroy(w->ev_join);
   if (w->ev_mid) (void)hipEventDestroy(w->ev_mid);
@@ -800,7 +974,8 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   // best candidate of one launch; its time (ms, two timed runs) in *tbest
   auto tune_one = [&](Launch& L, int mode_override, float* tbest, bool couple = false) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
-    const int kcs[11] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8};  // 0: pipelined, 1-8: balanced (64 vectors only)
+    // 0: pipelined, 1-8: balanced (64 vectors only), kWaveRows: a wave per row (rows of <= 64 outputs)
+    const int kcs[12] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8, kWaveRows};
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
     int best_kc = L.kcp[pi], best_remap = L.remapp[pi];
@@ -809,9 +984,11 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
       if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
       if (kc >= 0 && kc <= 8 && nvp != 64) continue;
       if (kc >= 1 && kc <= 8 && L.max_rows > 64) continue;
+      if (kc == kWaveRows && L.max_rows > 64) continue;
       for (int64_t g : grids)
         for (int remap = 0; remap < 2; ++remap) {
           if (g != 0 && g >= L.row_count) continue;
+          if (kc == kWaveRows && remap) continue;  // rows taken grid-stride
           // the dense rows run beside the sweeps: a persistent grid would hold
           // every CU slot and starve them, so they keep one workgroup per row
           if (g != 0 && !L.lowrank) continue;
@@ -857,7 +1034,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     }
     return H2_OK;
   };
-  float t_up = 0, t_down = 0, tc = 0, tcl = 0, td1 = 0, td2 = 0, tl1 = 0, tl2 = 0;
+  float t_up = 0, t_down = 0, t_out = 0, tc = 0, tcl = 0, td1 = 0, td2 = 0, tl1 = 0, tl2 = 0;
   rc = tune_list(plan.up, &t_up);
   if (rc == H2_OK) rc = tune_list(plan.down, &t_down);
   if (rc == H2_OK) rc = tune_list(plan.couple, &tc, true);
@@ -866,10 +1043,31 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if (rc == H2_OK) rc = tune_list(plan.dense2, &td2);
   if (rc == H2_OK) rc = tune_list(plan.dense_loc, &tl1);
   if (rc == H2_OK) rc = tune_list(plan.dense2_loc, &tl2);
-  if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM, nullptr);
+  if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM, &t_out);
   if (rc == H2_OK) {
     h->couple_mode[prec] = tcl < tc ? 1 : 0;
     h->dense_mode[prec] = tl1 + tl2 < td1 + td2 ? 1 : 0;
+  }
+  // fused sweeps (both directions, leaf expansion included) against the tuned
+  // per-level launches, two timed runs each after a warm-up
+  if (rc == H2_OK && prec != H2_PREC_BF16 && h->tree_ok && w.zx) {
+    float tf = 0.0f;
+    for (int rep = 0; rep < 3 && rc == H2_OK; ++rep) {
+      HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
+      rc = run_tree(h, w, h->tree_up, nvp, prec, s);
+      if (rc == H2_OK) rc = run_tree(h, w, h->tree_down, nvp, prec, s);
+      HIP_TRY(hipEventRecord(e1, s), "hipEventRecord");
+      HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (rep > 0) tf += ms;
+    }
+    const float tl = t_up + t_down + t_out;
+    if (rc == H2_OK) {
+      h->sweep_fused[prec] = tf < tl ? 1 : 0;
+      h->sweep_ms[prec][0] = tl / 2;
+      h->sweep_ms[prec][1] = tf / 2;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -882,8 +1080,8 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
     set_error("unknown precision");
     return H2_EINVAL;
   }
-  if (!(kc >= 0 && kc <= 8) && kc != 32 && kc != 64) {
-    set_error("kc must be 0-8, 32 or 64");
+  if (!(kc >= 0 && kc <= kWaveRows) && kc != 32 && kc != 64) {
+    set_error("kc must be 0-9, 32 or 64");
     return H2_EINVAL;
   }
   if (prec == H2_PREC_BF16 && kc != 64) { set_error("the BF16 kernel has kc 64 only"); return H2_EINVAL; }
@@ -912,6 +1110,19 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
   return H2_OK;
 }
 
+int h2_set_sweeps(h2_handle h, int prec, int fused) {
+  if (!h) { set_error("null handle"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32) { set_error("sweeps are chosen for FP64 and FP32"); return H2_EINVAL; }
+  if (fused && !h->tree_ok) {
+    set_error("this operator has rows that the fused sweeps do not take (more than 64 outputs)");
+    return H2_EUNSUPPORTED;
+  }
+  DeviceGuard guard(h->device);
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  h->sweep_fused[prec] = fused ? 1 : 0;
+  return H2_OK;
+}
+
 int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
   if (!h || !needed) { set_error("null handle or size output"); return H2_EINVAL; }
   std::string t;
@@ -936,6 +1147,17 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
       t += "\n";
     }
   };
+  for (int p = 0; p < 2; ++p) {
+    std::snprintf(line, sizeof line, "%s: sweeps %s (per-level %.3fms, fused %.3fms when tuned)\n", pn[p],
+                  h->tree_ok && h->sweep_fused[p] ? "fused" : "per level", h->sweep_ms[p][0], h->sweep_ms[p][1]);
+    t += line;
+  }
+  for (const auto* v : {&h->tree_up, &h->tree_down})
+    for (const TreeGroup& G : *v) {
+      std::snprintf(line, sizeof line, "%s tree workgroups=%lld levels=%d max_rows=%d\n",
+                    v == &h->tree_up ? "up" : "down", (long long)G.nwg, G.lv.nlev, G.max_rows);
+      t += line;
+    }
   const Plan& P = h->planN;
   dump("up", P.up);
   dump("couple", P.couple);
@@ -958,6 +1180,13 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
 int h2_stats(h2_handle h, h2_stats_t* st) {
   if (!h || !st) { set_error("null handle or output"); return H2_EINVAL; }
   *st = h->stats;
+  return H2_OK;
+}
+
+int h2_level_stats(h2_handle h, int64_t level, h2_level_stats_t* out) {
+  if (!h || !out) { set_error("null handle or output"); return H2_EINVAL; }
+  if (level < 0 || level >= (int64_t)h->level_stats.size()) { set_error("level out of range"); return H2_EINVAL; }
+  *out = h->level_stats[level];
   return H2_OK;
 }
 

@@ -210,6 +210,13 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
 
 int run_blaunch(h2_batch_s* b, const Launch& L, hipStream_t s) {
   const double* data = L.arr == ARR_TRANS ? b->d_trans : b->d_mat;
+  if (L.kc == kWaveRows && L.max_rows <= 64) {
+    const hipError_t e = launch_wave_rows<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend,
+                                                  b->rt.d_in_off, data, b->d_ws, b->d_ws, (int)b->nvp, L.mode,
+                                                  L.max_rows, s, L.grid);
+    if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
+    return H2_OK;
+  }
   hipError_t e = launch_rows_mfma<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend, b->rt.d_in_off,
                                           data, b->d_ws, b->d_ws, (int)b->nvp, L.mode, L.max_rows, s, L.kc, L.grid);
   if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
@@ -363,7 +370,7 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
   hipEvent_t e0, e1;
   HIP_TRYB(hipEventCreate(&e0), "hipEventCreate");
   HIP_TRYB(hipEventCreate(&e1), "hipEventCreate");
-  const int kcs[2] = {32, 64};
+  const int kcs[3] = {32, 64, kWaveRows};  // chunk widths of the LDS-staged kernel; a wave per row
   const int64_t grids[4] = {0, 1024, 2048, 4096};
   for (auto* v : {&b->up, &b->couple, &b->down, &b->dense, &b->out})
     for (Launch& L : *v) {
@@ -373,6 +380,7 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
       for (int kc : kcs)
         for (int64_t gsz : grids) {
           if (gsz != 0 && gsz >= L.row_count) continue;
+          if (kc == kWaveRows && L.max_rows > 64) continue;
           Launch T = L;
           T.kc = kc;
           T.grid = gsz;

@@ -7,6 +7,7 @@
 
 #include <array>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -127,6 +128,26 @@ struct Plan {
   Launch out;                  // leaf expansion + dense partial + alpha/beta update
 };
 
+// Fused sweeps of the multi-vector path (h2_tree_kernels.hip): the levels
+// one launch runs, in order, with their input and output buffers (0 X~, 1 x^,
+// 2 y^, 3 the leaf-expansion output) and epilogue (MODE_STORE / MODE_ACCUM).
+constexpr int kMaxTreeLevels = 8;
+struct TreeLevels {
+  int nlev = 0;
+  int in[kMaxTreeLevels] = {};
+  int out[kMaxTreeLevels] = {};
+  int mode[kMaxTreeLevels] = {};
+};
+// One fused launch: workgroup w owns the subtree of the w-th node of its
+// root level; ranges [range_off + w * nlev + lev] are its rows on each level.
+struct TreeGroup {
+  TreeLevels lv;
+  int64_t nwg = 0;
+  int64_t range_off = 0;
+  int max_rows = 0;
+  bool trans_data = false;  // rows read the transposed basis copies (upsweep)
+};
+
 struct Epilogue {
   const double* zn;     // dense partial, n x nv (ld n)
   const int32_t* perm;  // tree position -> original index
@@ -202,6 +223,8 @@ int64_t row_work(const RowSpec& r);
 struct Workspace {
   int64_t n = 0, H = 0, cap = 0;
   double *xt = nullptr, *xh = nullptr, *yh = nullptr, *zn = nullptr;
+  // leaf-expansion output of the fused sweeps (n * cap; cap >= kPassVectorsMfma only)
+  double* zx = nullptr;
   // FP32 copy of x^ (H * cap floats; cap >= kPassVectorsMfma only) that the
   // FP32 variant's 64-vector coupling launches gather from
   float* xh32 = nullptr;
@@ -222,6 +245,9 @@ int64_t ws_bytes(int64_t n, int64_t H, int64_t cap);
 // `buf`; otherwise `buf` holds the bytes before the dense section only and
 // the dense blocks are copied from device memory at d_dense (same device).
 int load_handle(const uint8_t* buf, int64_t len, int device, const double* d_dense, h2_handle* out);
+// True when products in precision `prec` need no preparation (allocation)
+// on this handle.
+bool prepared(h2_op_s* h, int prec);
 
 }  // namespace h2
 
@@ -232,6 +258,7 @@ struct h2_op_s {
   bool shared = true;
   std::vector<h2::LevelInfo> lv;
   h2_stats_t stats{};
+  std::vector<h2_level_stats_t> level_stats;
   // device data
   double* d_mat = nullptr;    // U, E, V, F, S, D (section layout of the buffer kept)
   double* d_trans = nullptr;  // transposed copies: U^T, E^T (and V^T, F^T)
@@ -241,6 +268,7 @@ struct h2_op_s {
   float* d_trans32 = nullptr;
   void* d_mat16 = nullptr;    // BF16 copies of the op-'N' low-rank rows, row-major per row
   void* d_trans16 = nullptr;
+  std::mutex prep_mu;         // guards the lazy creation of the FP32 and BF16 copies
   int32_t* d_perm = nullptr;
   int32_t* d_pinv = nullptr;  // original index -> tree position
   bool mfma_ok = true;        // every op-'N' launch fits the MFMA row kernel
@@ -253,6 +281,13 @@ struct h2_op_s {
   h2::RowTables wide;         // rows too wide for the tabled kernel
   h2::GatherTables gt;        // transposed rows of the 'T' plan
   h2::Plan planN, planT;
+  // fused sweeps of the op-'N' multi-vector path: upsweep groups (deepest
+  // first) and downsweep groups (the last one ends with the leaf expansion)
+  std::vector<h2::TreeGroup> tree_up, tree_down;
+  int2* d_tree_ranges = nullptr;
+  bool tree_ok = false;              // every group fits the fused kernel
+  int sweep_fused[3] = {1, 1, 1};    // per precision (FP64, FP32; BF16 has none): use the fused sweeps
+  float sweep_ms[3][2] = {};         // tuned times of the sweeps: per level, fused
   int64_t index_bytes = 0;
   // the serialized header and index sections (bytes before U), 8-byte aligned,
   // and the representation's total size: the host view of the structure
@@ -308,6 +343,20 @@ hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pin
                                 int nvp, hipStream_t s);
 hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double alpha, double beta, double* Y,
                                  int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s);
+// The multi-vector row product with one wave per row (kc code kWaveRows of
+// the tuner); grid = workgroups (0: enough for every row at once)
+constexpr int kWaveRows = 9;
+template <typename T>
+hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                            const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
+                            hipStream_t s, int64_t grid);
+template <typename T>
+hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
+                       const int32_t* colend, const int64_t* in_off, const T* data, double* const bufs[4], int nvp,
+                       int max_rows, hipStream_t s);
+// Y[j, v] = alpha * (Z[pinv[j], v] + Z2[pinv[j], v]) + beta * Y[j, v] (Z, Z2 row-major nvp, tree order)
+hipError_t launch_permute_out_rm2(const double* Z, const double* Z2, const int32_t* pinv, double alpha, double beta,
+                                  double* Y, int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s);
 hipError_t launch_rows_wide(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const double* data, const double* in, double* out, int nv, hipStream_t s);
 template <typename T>

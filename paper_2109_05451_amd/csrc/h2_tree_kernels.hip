@@ -1,0 +1,309 @@
+// Subtree-fused sweeps of the multi-vector path (FP64 and FP32 MFMA).
+//
+// The upsweep (Algorithm 1: leaf products x^_t = V_t^T x_t, then the transfer
+// levels x^_p = sum_c F_c^T x^_c) and the downsweep (Algorithm 6: y^_c +=
+// E_c y^_parent level by level, then the leaf expansion U_t y^_t) are chains
+// of small dependent products.  Launched level by level they are latency
+// bound: every level is a launch, and every row's matrix (a few KB) is one
+// workgroup's whole job.  Here one workgroup owns a subtree and runs several
+// levels of it, bottom-up or top-down, in one launch: a level's rows are
+// independent (one wave per row, no LDS), a barrier separates levels, and
+// each level reads what the previous level of the same workgroup wrote.
+// The node ranges of a subtree are contiguous on every level (children are
+// stored contiguously, in parent order), so a workgroup's rows on a level are
+// one range of the level's row list.
+//
+// Every output sums the same four-column steps, in the same order, with the
+// same MFMA instruction and fragment layout as the row kernels of
+// h2_kernels.hip (A[i][k] at lane i + 16k, B[k][j] at lane j + 16k, padded
+// steps reading zeros): the results are bitwise those of the per-level
+// launches.
+#include "h2_internal.h"
+
+namespace h2 {
+namespace {
+
+constexpr int kT = 256;
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ d4 op(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane l: row 4r + l/16, column l%16
+  static __device__ __forceinline__ int row(int r, int akk) { return 4 * r + akk; }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ f4 op(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane l: row 4(l/16) + r, column l%16
+  static __device__ __forceinline__ int row(int r, int akk) { return 4 * akk + r; }
+};
+
+__device__ __forceinline__ double* pick(int i, double* b0, double* b1, double* b2, double* b3) {
+  return i == 0 ? b0 : i == 1 ? b1 : i == 2 ? b2 : b3;
+}
+
+// One row on one wave, vector tiles vt0 .. vt0 + NTW - 1 of it: out (m x
+// 16NT, row-major rows of 16NT) = M (m x ncols, column-major at
+// data + R.data_off) times the input gathered block by block (row
+// in_off[b] + j of `in` for column j of block b).  Each lane keeps a cursor
+// over the row's blocks; its column grows by four per step.
+template <typename T, int NT, int NTW, int MT>
+__device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* __restrict__ colend,
+                                         const int64_t* __restrict__ in_off, const T* __restrict__ data,
+                                         const double* in, double* out, int mode, int lane, int vt0) {
+  typedef typename Mfma<T>::acc CT;
+  constexpr int NVP = 16 * NT;
+  const int m = R.nrows;
+  const int nb = R.blk_end - R.blk_begin;
+  if (m <= 0) return;
+  const int ncols = nb > 0 ? colend[R.blk_end - 1] : 0;
+  const int mt = (m + 15) >> 4;
+  const int arow = lane & 15, akk = lane >> 4;
+  CT acc[MT][NTW];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[i][j] = CT{0, 0, 0, 0};
+  int b = R.blk_begin, bstart = 0;
+  int bend = nb > 0 ? colend[b] : 0;
+  int64_t boff = nb > 0 ? in_off[b] : 0;
+  const T* M = data + R.data_off;
+  // four-column steps loaded per iteration: four, or two when the
+  // accumulators are many (keeps two waves per SIMD at 64 rows x 64 vectors)
+  constexpr int U = MT * NTW > 8 ? 2 : 4;
+  for (int c0 = 0; c0 < ncols; c0 += 4 * U) {
+    T a[U][MT], bf[U][NTW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = c0 + 4 * u + akk;
+      const bool ok = col < ncols;
+      if (ok) {
+        while (col >= bend) {
+          bstart = bend;
+          ++b;
+          bend = colend[b];
+          boff = in_off[b];
+        }
+      }
+      const double* src = in + (boff + (col - bstart)) * NVP + 16 * vt0 + arow;
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) bf[u][j] = ok ? (T)src[16 * j] : (T)0;
+#pragma unroll
+      for (int ti = 0; ti < MT; ++ti) {
+        const int r = 16 * ti + arow;
+        a[u][ti] = (ok && ti < mt && r < m) ? __builtin_nontemporal_load(M + r + (int64_t)m * col) : (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c0 + 4 * u < ncols) {
+#pragma unroll
+        for (int ti = 0; ti < MT; ++ti) {
+          if (ti < mt) {
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) acc[ti][j] = Mfma<T>::op(a[u][ti], bf[u][j], acc[ti][j]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int ti = 0; ti < MT; ++ti) {
+    if (ti >= mt) break;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * ti + Mfma<T>::row(r, akk);
+        if (a < m) {
+          double* o = out + (R.out_off + a) * NVP + 16 * (vt0 + j) + arow;
+          if (mode == MODE_STORE) *o = (double)acc[ti][j][r];
+          else *o += (double)acc[ti][j][r];
+        }
+      }
+  }
+}
+
+// One launch of a fused sweep: workgroup w takes, for each of the group's
+// levels in order, the rows ranges[w * nlev + lev] of the row table.  A row
+// is computed by NT / NTW waves, each with NTW of its vector tiles (two waves
+// per row when one wave's accumulators would leave one wave per SIMD), so
+// the four waves hold 4 NTW / NT rows at a time.  Buffers: 0 X~, 1 x^, 2 y^,
+// 3 the leaf-expansion output.
+template <typename T, int NT, int NTW, int MT>
+__global__ __launch_bounds__(kT) void k_tree(const int2* __restrict__ ranges, TreeLevels L,
+                                             const RowDesc* __restrict__ rows, const int32_t* __restrict__ colend,
+                                             const int64_t* __restrict__ in_off, const T* __restrict__ data,
+                                             double* b0, double* b1, double* b2, double* b3) {
+  constexpr int WPR = NT / NTW, RPW = 4 / WPR;  // waves per row, rows per workgroup at a time
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slot = wave / WPR, vt0 = (wave % WPR) * NTW;
+  for (int lev = 0; lev < L.nlev; ++lev) {
+    if (lev > 0) __syncthreads();  // the previous level's outputs are this level's inputs
+    const int2 rr = ranges[(int64_t)blockIdx.x * L.nlev + lev];
+    const double* in = pick(L.in[lev], b0, b1, b2, b3);
+    double* out = pick(L.out[lev], b0, b1, b2, b3);
+    for (int ri = rr.x + slot; ri < rr.y; ri += RPW)
+      wave_row<T, NT, NTW, MT>(rows[ri], colend, in_off, data, in, out, L.mode[lev], lane, vt0);
+  }
+}
+
+// A plain row list with the same wave-per-row product: workgroup b holds
+// 4 NTW / NT rows at a time, rows taken grid-stride.  One more form of the
+// multi-vector row launches for the tuner (no LDS, no barriers: the matrix
+// and input fragments are read straight from memory, many rows in flight
+// per CU).
+template <typename T, int NT, int NTW, int MT>
+__global__ __launch_bounds__(kT) void k_wave_rows(const RowDesc* __restrict__ rows, int64_t nrows,
+                                                  const int32_t* __restrict__ colend,
+                                                  const int64_t* __restrict__ in_off, const T* __restrict__ data,
+                                                  const double* in, double* out, int mode) {
+  constexpr int WPR = NT / NTW, RPW = 4 / WPR;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slot = wave / WPR, vt0 = (wave % WPR) * NTW;
+  for (int64_t ri = (int64_t)blockIdx.x * RPW + slot; ri < nrows; ri += (int64_t)gridDim.x * RPW)
+    wave_row<T, NT, NTW, MT>(rows[ri], colend, in_off, data, in, out, mode, lane, vt0);
+}
+
+// Y[j, v] = alpha * (Z[pinv[j], v] + Z2[pinv[j], v]) + beta * Y[j, v]: the
+// dense partial plus the leaf expansion (row-major NVP, tree order) into the
+// caller's column-major Y, through an LDS tile of 64 points so that both
+// sides are accessed with coalesced loads and stores.
+constexpr int kPermTile = 64;
+template <int NVP>
+__global__ __launch_bounds__(256) void k_permute_out_rm2(const double* __restrict__ Z, const double* __restrict__ Z2,
+                                                         const int32_t* __restrict__ pinv, double alpha, double beta,
+                                                         double* __restrict__ Y, int64_t ldy, int64_t n, int nv) {
+  constexpr int LD = NVP + 1, PER = kPermTile * NVP / 256;
+  __shared__ double tile[kPermTile * LD];
+  const int64_t j0 = blockIdx.x * (int64_t)kPermTile;
+  const int rows = (int)min<int64_t>(kPermTile, n - j0);
+  double r[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    if (jj < rows && v < nv) {
+      const int64_t src = (int64_t)pinv[j0 + jj] * NVP + v;
+      r[i] = __builtin_nontemporal_load(Z + src) + __builtin_nontemporal_load(Z2 + src);
+    } else {
+      r[i] = 0.0;
+    }
+  }
+  double yv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    yv[i] = beta != 0.0 && jj < rows && v < nv ? Y[j0 + jj + ldy * v] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    tile[jj * LD + v] = r[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    if (jj < rows && v < nv) {
+      const double z = alpha * tile[jj * LD + v];
+      Y[j0 + jj + ldy * v] = beta == 0.0 ? z : z + beta * yv[i];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_permute_out_rm2(const double* Z, const double* Z2, const int32_t* pinv, double alpha, double beta,
+                                  double* Y, int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nvp > kPassVectorsMfma || nv > nvp) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((n + kPermTile - 1) / kPermTile)), b(256);
+  switch (nvp) {
+    case 16: hipLaunchKernelGGL(k_permute_out_rm2<16>, g, b, 0, s, Z, Z2, pinv, alpha, beta, Y, ldy, n, nv); break;
+    case 32: hipLaunchKernelGGL(k_permute_out_rm2<32>, g, b, 0, s, Z, Z2, pinv, alpha, beta, Y, ldy, n, nv); break;
+    case 48: hipLaunchKernelGGL(k_permute_out_rm2<48>, g, b, 0, s, Z, Z2, pinv, alpha, beta, Y, ldy, n, nv); break;
+    case 64: hipLaunchKernelGGL(k_permute_out_rm2<64>, g, b, 0, s, Z, Z2, pinv, alpha, beta, Y, ldy, n, nv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
+                            const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
+                            hipStream_t s, int64_t grid) {
+  if (nrows == 0) return hipSuccess;
+  if (max_rows > 64) return hipErrorInvalidValue;
+#define H2_WR(NT, MT)                                                                                    \
+  do {                                                                                                   \
+    constexpr int NTW = (MT * NT > 8 && NT % 2 == 0) ? NT / 2 : NT, RPW = 4 / (NT / NTW);               \
+    const int64_t need = (nrows + RPW - 1) / RPW;                                                        \
+    const dim3 g((unsigned)(grid > 0 && grid < need ? grid : need)), b(kT);                              \
+    hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT>), g, b, 0, s, rows, nrows, colend, in_off, data, in, out, \
+                       mode);                                                                            \
+  } while (0)
+#define H2_WR_NT(NT)                          \
+  do {                                        \
+    if (max_rows <= 16) H2_WR(NT, 1);         \
+    else if (max_rows <= 32) H2_WR(NT, 2);    \
+    else if (max_rows <= 48) H2_WR(NT, 3);    \
+    else H2_WR(NT, 4);                        \
+  } while (0)
+  switch (nvp) {
+    case 16: H2_WR_NT(1); break;
+    case 32: H2_WR_NT(2); break;
+    case 48: H2_WR_NT(3); break;
+    case 64: H2_WR_NT(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef H2_WR_NT
+#undef H2_WR
+  return hipGetLastError();
+}
+template hipError_t launch_wave_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
+                                             const double*, double*, int, int, int, hipStream_t, int64_t);
+template hipError_t launch_wave_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
+                                            const double*, double*, int, int, int, hipStream_t, int64_t);
+
+template <typename T>
+hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
+                       const int32_t* colend, const int64_t* in_off, const T* data, double* const bufs[4], int nvp,
+                       int max_rows, hipStream_t s) {
+  if (nwg == 0 || L.nlev == 0) return hipSuccess;
+  if (L.nlev > kMaxTreeLevels || max_rows > 64) return hipErrorInvalidValue;
+  const dim3 g((unsigned)nwg), b(kT);
+#define H2_TREE(NT, MT)                                                                                      \
+  hipLaunchKernelGGL((k_tree<T, NT, (MT * NT > 8 && NT % 2 == 0 ? NT / 2 : NT), MT>), g, b, 0, s, ranges, L, rows, \
+                     colend, in_off, data, bufs[0], bufs[1], bufs[2], bufs[3])
+#define H2_TREE_NT(NT)                   \
+  do {                                   \
+    if (max_rows <= 16) H2_TREE(NT, 1);  \
+    else if (max_rows <= 32) H2_TREE(NT, 2); \
+    else if (max_rows <= 48) H2_TREE(NT, 3); \
+    else H2_TREE(NT, 4);                 \
+  } while (0)
+  switch (nvp) {
+    case 16: H2_TREE_NT(1); break;
+    case 32: H2_TREE_NT(2); break;
+    case 48: H2_TREE_NT(3); break;
+    case 64: H2_TREE_NT(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef H2_TREE_NT
+#undef H2_TREE
+  return hipGetLastError();
+}
+template hipError_t launch_tree<double>(const int2*, int64_t, const TreeLevels&, const RowDesc*, const int32_t*,
+                                        const int64_t*, const double*, double* const[4], int, int, hipStream_t);
+template hipError_t launch_tree<float>(const int2*, int64_t, const TreeLevels&, const RowDesc*, const int32_t*,
+                                       const int64_t*, const float*, double* const[4], int, int, hipStream_t);
+
+}  // namespace h2

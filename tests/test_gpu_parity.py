@@ -188,4 +188,19 @@ def test_reserve_and_stats():
     g.reserve(64)
     st2 = g.stats()
     assert st2["device_bytes"] > st["device_bytes"]
+    # algorithmic work (every stored entry read once; x^, y^ written and read once)
+    entries = sum(st["entries_" + k] for k in "UVEFSD")
+    assert st["alg_flops_per_vector"] == 2 * entries + st["n"]
+    assert st["alg_bytes_matrix"] == 8 * entries
+    assert st["alg_bytes_per_vector"] == 8 * (2 * st["n"] + 4 * st["tree_rows"])
+    # per-level structure adds up to the totals
+    ls = g.level_stats()
+    assert len(ls) == st["depth"] + 1
+    assert [x["nodes"] for x in ls] == [2 ** l for l in range(st["depth"] + 1)]
+    assert all(x["krow"] == x["kcol"] == 16 for x in ls)
+    assert sum(x["coupling_blocks"] for x in ls) == st["ncoupling"]
+    assert sum(x["entries_S"] for x in ls) == st["entries_S"]
+    assert sum(x["entries_E"] for x in ls) == st["entries_E"] == sum(x["entries_F"] for x in ls)
+    assert max(x["csp"] for x in ls) == st["csp"]
+    assert ls[0]["coupling_blocks"] == 0 and ls[0]["entries_E"] == 0
     g.close()

@@ -123,27 +123,78 @@ def test_tune_keeps_results_bitwise(cfg):
     g.close()
 
 
+# Grids of the multi-vector launches: one workgroup per row (0), persistent
+# grids smaller than every launch's row count here (8, 24: each workgroup
+# walks several rows, and with XCD-aware ranges each XCD's workgroups stride
+# through their contiguous eighth), and one larger than most launches (1024:
+# capped to one row per workgroup).
+GRIDS = (0, 8, 24, 1024)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_launch_settings_bitwise(prec):
     """Every fixed setting of the multi-vector launches (chunk width or the
-    pipelined kernel, grid, XCD mapping, row order) gives bitwise the same
-    product at 64 and 40 vectors."""
+    pipelined kernel, the wave-per-row kernel, grid, XCD mapping, row order)
+    gives bitwise the same
+    product at 64 and 40 vectors, and the FP64 product is the oracle's to the
+    1e-12 * B bar."""
     from paper_2109_05451_amd import H2Operator
     buf = np.array(h2gen.build(h2gen.points(5000, 2, 6), leaf=48, p=6, eta=0.7, kernel="exp").array, copy=True)
     ref = oracle.Oracle(buf)
     g = H2Operator(buf)
+    # every launch of the plan has more rows than the small grids
+    rows = [int(line.split("rows=")[1].split()[0]) for line in g.plan_info().splitlines() if "rows=" in line]
+    assert min(rows) >= 1 and sum(r > 24 for r in rows) >= 4
     for nv in (64, 40):
         X = h2gen.vectors(g.n, nv, 13)
         base = run(g, X, "N", precision=prec)
         if prec == "fp64":
             want, B = ref.gemv(X), ref.gemv(X, absval=True)
             assert np.all(np.abs(base - want) <= 1e-12 * B)
-        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 4, 5, 6, 7, 8, 32, 64)
+        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 32, 64)
         for kc in kcs:
-            for grid in (0, 1024):
+            for grid in GRIDS:
                 for xcd in (False, True):
                     for tree in (0, 1):
                         g.tune_set(prec, kc, grid, xcd, tree)
                         got = run(g, X, "N", precision=prec)
                         assert np.array_equal(got, base), (prec, nv, kc, grid, xcd, tree)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("rank", [16, 36, 64])
+def test_persistent_grids_walk_rows_against_oracle(prec, rank):
+    """The 4096-point 2D operator (rank 16), and rank-36 (2D) and rank-64 (3D)
+    operators of a few thousand points, with every launch on a persistent
+    grid of 8 or 24 workgroups (several rows each), XCD-aware or not, in
+    either row order: every output row against the oracle (bit-exact across
+    settings; FP64 within 1e-12 * B, FP32 2e-5 * B, BF16 5e-2 * B)."""
+    from paper_2109_05451_amd import H2Operator
+    if rank == 16:
+        buf = np.array(h2gen.build_config("c1_2d_4096").array, copy=True)
+    elif rank == 36:
+        buf = np.array(h2gen.build(h2gen.points(6000, 2, 16), leaf=64, p=6, eta=0.7, kernel="exp").array,
+                       copy=True)
+    else:
+        buf = np.array(h2gen.build(h2gen.points(6000, 3, 17), leaf=64, p=4, eta=0.7, kernel="laplace").array,
+                       copy=True)
+    ref = oracle.Oracle(buf)
+    g = H2Operator(buf)
+    X = h2gen.vectors(g.n, 64, 14)
+    want, B = ref.gemv(X), ref.gemv(X, absval=True)
+    tol = {"fp64": 1e-12, "fp32": TOL32, "bf16": TOL16}[prec]
+    kcs = (64,) if prec == "bf16" else (0, 5, 8, 9, 32, 64)
+    first = None
+    for kc in kcs:
+        for grid in (8, 24):
+            for xcd in (False, True):
+                for tree in (0, 1):
+                    g.tune_set(prec, kc, grid, xcd, tree)
+                    got = run(g, X, "N", precision=prec)
+                    if first is None:
+                        first = got
+                        assert np.all(np.abs(got - want) <= tol * B), (prec, rank, np.max(np.abs(got - want) / B))
+                    assert np.array_equal(got, first), (prec, rank, kc, grid, xcd, tree)
+    g.close()
+    ref.close()
