@@ -160,6 +160,25 @@ int h2_gemv(h2_handle h, char op, double alpha, const double* X, int64_t ldx, in
 int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
                double beta, double* Y, int64_t ldy, int prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * product of h2_gemv, same arguments and semantics, with its scratch (the
+ * tree-ordered input, the vector trees x^ and y^, the dense partial) in one
+ * fixed device array of 64 MiB per GPU that the library holds until the
+ * process ends, instead of the handle's workspace.  The call allocates no
+ * memory and creates no stream or event (those are made by h2_load).
+ * Vectors go in passes of up to 4 columns, as many as fit; one column needs
+ * 8 * (2 n + 2 H) bytes, n the matrix order and H = tree_rows of h2_stats,
+ * so operators with n + H above 4 Mi rows are refused.  The array is shared
+ * by every call on its GPU, whatever the handle, and keeps the last call's
+ * contents (no call relies on its initial contents): calls that overlap on
+ * one GPU -- on different streams, or from different host threads -- race
+ * and give wrong results; calls in order on one stream do not.
+ * Errors: as h2_gemv, plus H2_EUNSUPPORTED when one column of scratch does
+ * not fit the array. */
+int h2_gemv_noalloc(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
+                    double beta, double* Y, int64_t ldy, void* stream);
+
 /* Build the device copy of the low-rank data in precision `prec` now
  * (no-op for H2_PREC_FP64 or when it exists).  Synchronous. */
 int h2_prepare(h2_handle h, int prec);

@@ -146,6 +146,7 @@ void free_device(h2_op_s* h) {
       if (e) (void)hipEventDestroy(e);
   h->ev_pool.clear();
   ws_destroy(&h->ws);
+  ws_destroy(&h->na);
 }
 
 // Fused sweeps of the op-'N' multi-vector path.  Level boundaries
@@ -530,6 +531,17 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, con
     set_error("out of host memory while building schedules");
     rc = H2_ENOMEM;
   }
+  // the no-allocation product's stream and events, and the device address
+  // of its scratch array on this device
+  if (rc == H2_OK) {
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&h->na.side, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->na.ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->na.ev_join, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->na.ev_mid, hipEventDisableTiming)) != hipSuccess)
+      rc = hip_fail(e, "stream and events of the no-allocation product");
+  }
+  if (rc == H2_OK) rc = scratch_attach(device);
   if (rc != H2_OK) {
     free_device(h);
     delete h;
@@ -871,7 +883,8 @@ int gemv_ws(h2_op_s* h, const Workspace& w, bool trans, double alpha, const doub
   }
   // multi-vector products of op 'N' (and every BF16 product) go to the MFMA kernels
   const bool mfma = !trans && h->mfma_ok && w.cap >= kPassVectorsMfma && (nv > kPassVectors || prec == H2_PREC_BF16);
-  const int64_t pass = mfma ? kPassVectorsMfma : kPassVectors;
+  // (a workspace with fewer than kPassVectors columns takes passes of its width)
+  const int64_t pass = mfma ? kPassVectorsMfma : std::min<int64_t>(kPassVectors, w.cap);
   for (int64_t v0 = 0; v0 < nv; v0 += pass) {
     const int nvc = (int)std::min<int64_t>(pass, nv - v0);
     rc = gemv_pass(h, w, trans, alpha, X + ldx * v0, ldx, nvc, beta, Y + ldy * v0, ldy, s,

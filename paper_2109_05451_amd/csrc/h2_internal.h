@@ -245,6 +245,9 @@ int64_t ws_bytes(int64_t n, int64_t H, int64_t cap);
 // `buf`; otherwise `buf` holds the bytes before the dense section only and
 // the dense blocks are copied from device memory at d_dense (same device).
 int load_handle(const uint8_t* buf, int64_t len, int device, const double* d_dense, h2_handle* out);
+// Look up, once per device, the device address of the fixed scratch array of
+// h2_gemv_noalloc (h2_noalloc.hip); `device` is current.  Called by every load.
+int scratch_attach(int device);
 // True when products in precision `prec` need no preparation (allocation)
 // on this handle.
 bool prepared(h2_op_s* h, int prec);
@@ -295,6 +298,9 @@ struct h2_op_s {
   std::vector<uint64_t> prefix;
   int64_t prefix_len = 0, file_len = 0;
   h2::Workspace ws;  // the handle's own workspace (h2_gemv), allocated on first use
+  // side stream and fork/join events of h2_gemv_noalloc, created at load
+  // (its buffers are views of the fixed scratch array)
+  h2::Workspace na;
   // profiling
   bool profiling = false;
   std::vector<std::array<hipEvent_t, 11>> ev_pool;
