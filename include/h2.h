@@ -264,6 +264,15 @@ int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
  * reproducible timing and for tests.  Errors: H2_EINVAL. */
 int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_order);
 
+/* Workgroups of the dense near-field launches on the multi-vector path
+ * (more than 4 vectors): -1 (the default) the grid h2_tune picked, 0 one
+ * workgroup per row, a positive count a persistent grid of that many.  The
+ * dense rows run on a second stream beside the latency-bound sweeps; a
+ * persistent grid holds fewer CU slots, so the sweeps' small launches start
+ * sooner.  Results do not change.  Synchronizes the device.
+ * Errors: H2_EINVAL. */
+int h2_set_dense_grid(h2_handle h, int64_t workgroups);
+
 /* How the multi-vector path (op 'N', 64-vector passes or fewer, FP64 and
  * FP32) runs the upsweep, the downsweep and the leaf expansion: fused != 0
  * in a few launches in which each workgroup runs several levels of one

@@ -577,20 +577,24 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   double* out = bufs[mode_override >= 0 ? BUF_ZN : L.out];
   const int mode = mode_override >= 0 ? mode_override : L.mode;
   hipError_t e = hipSuccess;
+  // the dense rows' grid on the multi-vector path: the tuned one, or the
+  // handle's override (h2_set_dense_grid)
+  const int64_t grid_of = [&](int pi) {
+    return (!L.lowrank && h->dense_grid_mv >= 0) ? h->dense_grid_mv : L.gridp[pi];
+  }(lowp ? H2_PREC_FP32 : H2_PREC_FP64);
   if (nvp > 0 && L.kcp[lowp ? H2_PREC_FP32 : H2_PREC_FP64] == kWaveRows && L.max_rows <= 64) {
-    const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     e = lowp ? launch_wave_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.gridp[pi])
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of)
              : launch_wave_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.gridp[pi]);
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of);
   } else if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
     e = lowp ? launch_rows_mfma<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], grid_of,
                                        L.remapp[pi], in32)
              : launch_rows_mfma<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], L.gridp[pi],
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, L.kcp[pi], grid_of,
                                         L.remapp[pi]);
   } else if (L.kind == KIND_STREAM) {
     // the dense rows (beside the sweeps) hold two workgroup slots per CU, so
@@ -1120,6 +1124,14 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
       }
   h->couple_mode[prec] = tree_order != 0 ? 1 : 0;
   h->dense_mode[prec] = tree_order != 0 ? 1 : 0;
+  return H2_OK;
+}
+
+int h2_set_dense_grid(h2_handle h, int64_t workgroups) {
+  if (!h || workgroups < -1) { set_error("bad handle or workgroups"); return H2_EINVAL; }
+  DeviceGuard guard(h->device);
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  h->dense_grid_mv = workgroups;
   return H2_OK;
 }
 

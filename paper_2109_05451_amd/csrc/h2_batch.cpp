@@ -52,6 +52,8 @@ struct h2_batch_s {
   double* d_trans = nullptr;
   double* d_ws = nullptr;
   int32_t* d_pinv = nullptr;
+  int32_t *d_tile_op = nullptr, *d_tile_j0 = nullptr;  // permutation tiles (operator, first row)
+  int64_t ntiles = 0;
   h2::RowTables rt;
   std::vector<h2::Launch> up, couple, down, dense, out;
   h2::BatchItem* h_items = nullptr;  // pinned
@@ -69,7 +71,7 @@ namespace {
 
 void free_batch(h2_batch_s* b) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
-  F(b->d_mat); F(b->d_trans); F(b->d_ws); F(b->d_pinv); F(b->d_items);
+  F(b->d_mat); F(b->d_trans); F(b->d_ws); F(b->d_pinv); F(b->d_items); F(b->d_tile_op); F(b->d_tile_j0);
   F(b->rt.d_rows); F(b->rt.d_colend); F(b->rt.d_in_off);
   if (b->h_items) (void)hipHostFree(b->h_items);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -182,6 +184,14 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   }
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_pinv), sizeof(int32_t) * pinv.size()), "hipMalloc(pinv)");
   HIP_TRYB(hipMemcpy(b->d_pinv, pinv.data(), sizeof(int32_t) * pinv.size(), hipMemcpyHostToDevice), "hipMemcpy");
+  // permutation tiles: kPermTile original rows of one operator each
+  std::vector<int32_t> tile_op, tile_j0;
+  for (int64_t i = 0; i < count; ++i)
+    for (int64_t j0 = 0; j0 < P[i].n; j0 += kPermTile) {
+      tile_op.push_back((int32_t)i);
+      tile_j0.push_back((int32_t)j0);
+    }
+  b->ntiles = (int64_t)tile_op.size();
   // schedules
   auto up_tab = [&](auto& v, auto** d) -> int {
     if (v.empty()) return H2_OK;
@@ -191,7 +201,8 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   };
   int rc;
   if ((rc = up_tab(b->rt.rows, &b->rt.d_rows)) || (rc = up_tab(b->rt.colend, &b->rt.d_colend)) ||
-      (rc = up_tab(b->rt.in_off, &b->rt.d_in_off)))
+      (rc = up_tab(b->rt.in_off, &b->rt.d_in_off)) || (rc = up_tab(tile_op, &b->d_tile_op)) ||
+      (rc = up_tab(tile_j0, &b->d_tile_j0)))
     return rc;
   // workspace (row-major, nvp per row), zeroed once
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_ws), sizeof(double) * std::max<int64_t>(row, 1) * b->nvp),
@@ -226,7 +237,8 @@ int run_blaunch(h2_batch_s* b, const Launch& L, hipStream_t s) {
 // The launch sequence after the items are on the device.
 int batch_sequence(h2_batch_s* b, hipStream_t s) {
   int rc;
-  HIP_TRYB(launch_batch_permute(b->d_items, b->count, b->nmax, b->d_pinv, b->d_ws, (int)b->nvp, false, s),
+  HIP_TRYB(launch_batch_permute(b->d_items, b->d_tile_op, b->d_tile_j0, b->ntiles, b->d_pinv, b->d_ws, (int)b->nvp,
+                                false, s),
            "batch permute");
   HIP_TRYB(hipEventRecord(b->ev_fork, s), "hipEventRecord");
   HIP_TRYB(hipStreamWaitEvent(b->side, b->ev_fork, 0), "hipStreamWaitEvent");
@@ -239,7 +251,8 @@ int batch_sequence(h2_batch_s* b, hipStream_t s) {
   HIP_TRYB(hipStreamWaitEvent(s, b->ev_join, 0), "hipStreamWaitEvent");
   for (const Launch& L : b->out)
     if ((rc = run_blaunch(b, L, s))) return rc;
-  HIP_TRYB(launch_batch_permute(b->d_items, b->count, b->nmax, b->d_pinv, b->d_ws, (int)b->nvp, true, s),
+  HIP_TRYB(launch_batch_permute(b->d_items, b->d_tile_op, b->d_tile_j0, b->ntiles, b->d_pinv, b->d_ws, (int)b->nvp,
+                                true, s),
            "batch permute out");
   return H2_OK;
 }

@@ -278,6 +278,9 @@ struct h2_op_s {
   // workgroups of the dense launches on the streaming path (nv <= 4): two per
   // CU, a persistent grid that leaves the other slots to the sweeps beside it
   int64_t dense_stream_grid = 0;
+  // workgroups of the dense launches on the multi-vector path: -1 the tuned
+  // grid, 0 one per row, else a persistent grid (h2_set_dense_grid)
+  int64_t dense_grid_mv = -1;
   int couple_mode[3] = {0, 0, 0};  // per precision: 0 longest first, 1 tree order (h2_tune)
   int dense_mode[3] = {0, 0, 0};   // per precision: 0 longest first, 1 tree order (h2_tune)
   h2::RowTables rt;           // streaming rows of both plans
@@ -335,8 +338,10 @@ struct BatchItem {
   int64_t xt_row;    // its X~ rows in the workspace arena
   int64_t zn_row;    // its dense-partial rows in the workspace arena
 };
-hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t nmax, const int32_t* pinv,
-                                double* ws, int nvp, bool out, hipStream_t s);
+// tiles of kPermTile original rows: tile b is rows tile_j0[b] .. + 63 of operator tile_op[b]
+constexpr int kPermTile = 64;
+hipError_t launch_batch_permute(const BatchItem* items, const int32_t* tile_op, const int32_t* tile_j0,
+                                int64_t ntiles, const int32_t* pinv, double* ws, int nvp, bool out, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 // BF16 path (data: __bf16, rows stored row-major; see the kernel file)
 hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,

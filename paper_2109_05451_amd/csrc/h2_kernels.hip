@@ -233,7 +233,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // nvp vectors, so that both the column-major side (64 consecutive points of
 // one vector) and the tree-ordered side (one point's nvp vectors, contiguous)
 // are accessed with coalesced loads and stores.
-constexpr int kPermTile = 64;
 
 // xt[pinv[j], v] = X[j, v] for v < nv, 0 for nv <= v < NVP.  A workgroup
 // moves kPermTile original rows through LDS: every thread issues all of its
@@ -956,39 +955,100 @@ template hipError_t launch_rows_mfma<float>(const RowDesc*, int64_t, const int32
                                             const float*);
 
 
-// Batched input permutation: operator blockIdx.y, original index j.  Rows
-// of the workspace arena are row-major with nvp vectors; padding vectors,
-// operators with nv == 0 and alpha == 0 get zeros (X is then not read).
-__global__ void k_batch_permute_in(const BatchItem* __restrict__ items, const int32_t* __restrict__ pinv,
-                                   double* __restrict__ ws, int nvp) {
-  const BatchItem it = items[blockIdx.y];
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= it.n) return;
-  double* row = ws + (it.xt_row + pinv[it.pinv_off + j]) * nvp;
-  const bool use = it.nv > 0 && it.alpha != 0.0;
-  for (int v = 0; v < nvp; ++v) row[v] = (use && v < it.nv) ? it.X[j + it.ldx * v] : 0.0;
-}
-
-// Y_i[j, v] = alpha_i * Z_i[pinv_i[j], v] + beta_i * Y_i[j, v], v < nv_i.
-__global__ void k_batch_permute_out(const BatchItem* __restrict__ items, const int32_t* __restrict__ pinv,
-                                    const double* __restrict__ ws, int nvp) {
-  const BatchItem it = items[blockIdx.y];
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= it.n) return;
-  const double* row = ws + (it.zn_row + pinv[it.pinv_off + j]) * nvp;
-  for (int v = 0; v < it.nv; ++v) {
-    double* y = it.Y + j + it.ldy * v;
-    const double z = it.alpha == 0.0 ? 0.0 : it.alpha * row[v];
-    *y = it.beta == 0.0 ? z : z + it.beta * *y;
+// Batched permutations through an LDS tile of kPermTile original rows of one
+// operator: workgroup b takes tile b of the list (operator tile_op[b], first
+// original row tile_j0[b]), so no workgroup idles on a small operator, and
+// both the column-major side (64 consecutive points of one vector) and the
+// row-major workspace side (one point's NVP vectors) are accessed with
+// coalesced loads and stores.  In: rows xt_row + pinv[j] get X[j, v] for
+// v < nv, zeros for the padding vectors (and for nv == 0 or alpha == 0, when
+// X is not read).  Out: Y[j, v] = alpha Z[zn_row + pinv[j], v] + beta Y[j, v]
+// for v < nv (beta == 0: Y not read).
+template <int NVP>
+__global__ __launch_bounds__(256) void k_batch_permute_in(const BatchItem* __restrict__ items,
+                                                          const int32_t* __restrict__ tile_op,
+                                                          const int32_t* __restrict__ tile_j0,
+                                                          const int32_t* __restrict__ pinv, double* __restrict__ ws) {
+  constexpr int LD = NVP + 1, PER = kPermTile * NVP / 256;
+  __shared__ double tile[kPermTile * LD];
+  const BatchItem it = items[tile_op[blockIdx.x]];
+  const int64_t j0 = tile_j0[blockIdx.x];
+  const int rows = (int)min<int64_t>(kPermTile, it.n - j0);
+  const int nv = (it.nv > 0 && it.alpha != 0.0) ? (int)it.nv : 0;
+  double r[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    r[i] = jj < rows && v < nv ? __builtin_nontemporal_load(it.X + j0 + jj + it.ldx * v) : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    tile[jj * LD + v] = r[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    if (jj < rows) ws[(it.xt_row + pinv[it.pinv_off + j0 + jj]) * NVP + v] = tile[jj * LD + v];
   }
 }
 
-hipError_t launch_batch_permute(const BatchItem* items, int64_t count, int64_t nmax, const int32_t* pinv,
-                                double* ws, int nvp, bool out, hipStream_t s) {
-  if (count == 0 || nmax == 0) return hipSuccess;
-  const dim3 grid(grid1d(nmax, 256), (unsigned)count);
-  if (out) hipLaunchKernelGGL(k_batch_permute_out, grid, dim3(256), 0, s, items, pinv, ws, nvp);
-  else hipLaunchKernelGGL(k_batch_permute_in, grid, dim3(256), 0, s, items, pinv, ws, nvp);
+template <int NVP>
+__global__ __launch_bounds__(256) void k_batch_permute_out(const BatchItem* __restrict__ items,
+                                                           const int32_t* __restrict__ tile_op,
+                                                           const int32_t* __restrict__ tile_j0,
+                                                           const int32_t* __restrict__ pinv,
+                                                           const double* __restrict__ ws) {
+  constexpr int LD = NVP + 1, PER = kPermTile * NVP / 256;
+  __shared__ double tile[kPermTile * LD];
+  const BatchItem it = items[tile_op[blockIdx.x]];
+  if (it.nv <= 0) return;  // the operator is skipped: Y untouched (uniform over the workgroup)
+  const int64_t j0 = tile_j0[blockIdx.x];
+  const int rows = (int)min<int64_t>(kPermTile, it.n - j0);
+  const int nv = (int)it.nv;
+  double r[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    r[i] = jj < rows && v < nv && it.alpha != 0.0
+               ? __builtin_nontemporal_load(ws + (it.zn_row + pinv[it.pinv_off + j0 + jj]) * NVP + v)
+               : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, jj = e / NVP, v = e - jj * NVP;
+    tile[jj * LD + v] = r[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i, v = e / kPermTile, jj = e - v * kPermTile;
+    if (jj < rows && v < nv) {
+      double* y = it.Y + j0 + jj + it.ldy * v;
+      const double z = it.alpha == 0.0 ? 0.0 : it.alpha * tile[jj * LD + v];
+      *y = it.beta == 0.0 ? z : z + it.beta * *y;
+    }
+  }
+}
+
+hipError_t launch_batch_permute(const BatchItem* items, const int32_t* tile_op, const int32_t* tile_j0,
+                                int64_t ntiles, const int32_t* pinv, double* ws, int nvp, bool out, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  const dim3 g((unsigned)ntiles), b(256);
+#define H2_BP(NVP)                                                                                            \
+  do {                                                                                                        \
+    if (out) hipLaunchKernelGGL(k_batch_permute_out<NVP>, g, b, 0, s, items, tile_op, tile_j0, pinv, ws);     \
+    else hipLaunchKernelGGL(k_batch_permute_in<NVP>, g, b, 0, s, items, tile_op, tile_j0, pinv, ws);          \
+  } while (0)
+  switch (nvp) {
+    case 16: H2_BP(16); break;
+    case 32: H2_BP(32); break;
+    case 48: H2_BP(48); break;
+    case 64: H2_BP(64); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef H2_BP
   return hipGetLastError();
 }
 

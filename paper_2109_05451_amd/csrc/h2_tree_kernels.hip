@@ -53,16 +53,18 @@ __device__ __forceinline__ double* pick(int i, double* b0, double* b1, double* b
 // data + R.data_off) times the input gathered block by block (row
 // in_off[b] + j of `in` for column j of block b).  Each lane keeps a cursor
 // over the row's blocks; its column grows by four per step.
+// The row's block table is colend[b0 .. b0 + nb), in_off[b0 .. b0 + nb):
+// the global tables (b0 = R.blk_begin) or a wave's copy in LDS (b0 = 0).
 template <typename T, int NT, int NTW, int MT>
-__device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* __restrict__ colend,
-                                         const int64_t* __restrict__ in_off, const T* __restrict__ data,
-                                         const double* in, double* out, int mode, int lane, int vt0) {
+__device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* colend, const int64_t* in_off, int b0,
+                                         const T* __restrict__ data, const double* in, double* out, int mode,
+                                         int lane, int vt0) {
   typedef typename Mfma<T>::acc CT;
   constexpr int NVP = 16 * NT;
   const int m = R.nrows;
   const int nb = R.blk_end - R.blk_begin;
   if (m <= 0) return;
-  const int ncols = nb > 0 ? colend[R.blk_end - 1] : 0;
+  const int ncols = nb > 0 ? colend[b0 + nb - 1] : 0;
   const int mt = (m + 15) >> 4;
   const int arow = lane & 15, akk = lane >> 4;
   CT acc[MT][NTW];
@@ -70,7 +72,7 @@ __device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* __rest
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[i][j] = CT{0, 0, 0, 0};
-  int b = R.blk_begin, bstart = 0;
+  int b = b0, bstart = 0;
   int bend = nb > 0 ? colend[b] : 0;
   int64_t boff = nb > 0 ? in_off[b] : 0;
   const T* M = data + R.data_off;
@@ -150,34 +152,50 @@ __global__ __launch_bounds__(kT) void k_tree(const int2* __restrict__ ranges, Tr
     const int2 rr = ranges[(int64_t)blockIdx.x * L.nlev + lev];
     const double* in = pick(L.in[lev], b0, b1, b2, b3);
     double* out = pick(L.out[lev], b0, b1, b2, b3);
-    for (int ri = rr.x + slot; ri < rr.y; ri += RPW)
-      wave_row<T, NT, NTW, MT>(rows[ri], colend, in_off, data, in, out, L.mode[lev], lane, vt0);
+    for (int ri = rr.x + slot; ri < rr.y; ri += RPW) {
+      const RowDesc R = rows[ri];
+      wave_row<T, NT, NTW, MT>(R, colend, in_off, R.blk_begin, data, in, out, L.mode[lev], lane, vt0);
+    }
   }
 }
 
 // A plain row list with the same wave-per-row product: workgroup b holds
 // 4 NTW / NT rows at a time, rows taken grid-stride.  One more form of the
-// multi-vector row launches for the tuner (no LDS, no barriers: the matrix
-// and input fragments are read straight from memory, many rows in flight
-// per CU).
+// multi-vector row launches for the tuner: no barriers, the matrix and input
+// fragments read straight from memory, many rows in flight per CU.  Each
+// wave copies its row's block table into its own LDS region first, so the
+// column cursor (one step per block, dozens of blocks in a coupling or dense
+// row) reads LDS instead of waiting on dependent global loads.
 template <typename T, int NT, int NTW, int MT>
 __global__ __launch_bounds__(kT) void k_wave_rows(const RowDesc* __restrict__ rows, int64_t nrows,
                                                   const int32_t* __restrict__ colend,
                                                   const int64_t* __restrict__ in_off, const T* __restrict__ data,
                                                   const double* in, double* out, int mode) {
   constexpr int WPR = NT / NTW, RPW = 4 / WPR;
+  __shared__ int32_t s_end[4][kNbMax];
+  __shared__ int64_t s_in[4][kNbMax];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = wave / WPR, vt0 = (wave % WPR) * NTW;
-  for (int64_t ri = (int64_t)blockIdx.x * RPW + slot; ri < nrows; ri += (int64_t)gridDim.x * RPW)
-    wave_row<T, NT, NTW, MT>(rows[ri], colend, in_off, data, in, out, mode, lane, vt0);
+  for (int64_t ri = (int64_t)blockIdx.x * RPW + slot; ri < nrows; ri += (int64_t)gridDim.x * RPW) {
+    const RowDesc R = rows[ri];
+    const int nb = R.blk_end - R.blk_begin;  // <= kNbMax for rows of these tables
+    __builtin_amdgcn_wave_barrier();         // the previous row's table fully read
+    for (int i = lane; i < nb; i += 64) {
+      s_end[wave][i] = colend[R.blk_begin + i];
+      s_in[wave][i] = in_off[R.blk_begin + i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_row<T, NT, NTW, MT>(R, s_end[wave], s_in[wave], 0, data, in, out, mode, lane, vt0);
+  }
 }
 
 // Y[j, v] = alpha * (Z[pinv[j], v] + Z2[pinv[j], v]) + beta * Y[j, v]: the
 // dense partial plus the leaf expansion (row-major NVP, tree order) into the
 // caller's column-major Y, through an LDS tile of 64 points so that both
 // sides are accessed with coalesced loads and stores.
-constexpr int kPermTile = 64;
 template <int NVP>
 __global__ __launch_bounds__(256) void k_permute_out_rm2(const double* __restrict__ Z, const double* __restrict__ Z2,
                                                          const int32_t* __restrict__ pinv, double alpha, double beta,
