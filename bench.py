@@ -120,6 +120,37 @@ def sample_rows(n: int, seed: int, count: int = 192) -> np.ndarray:
     return np.unique(np.concatenate([[0, n // 2, n - 1], np.random.default_rng(seed).integers(0, n, count)]))
 
 
+def measured_peaks(torch) -> dict:
+    """The GPU's measured HBM read rate (a streaming kernel over 8 GiB) and
+    FP64 / BF16 matrix-core rates (loops of independent MFMA chains), from
+    the benchmark's probe library; None where it is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2109_05451_amd", "libh2peaks.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.h2p_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_float)]
+    lib.h2p_mfma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    nbytes = 8 << 30
+    buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ms = ctypes.c_float()
+    out = {}
+    if lib.h2p_read(buf.data_ptr(), nbytes, sink.data_ptr(), 5, ctypes.byref(ms)) == 0:
+        out["hbm_read_gbs"] = round(nbytes / (ms.value * 1e-3) / 1e9, 1)
+    del buf
+    fl = ctypes.c_double()
+    for name, bf16 in (("fp64_mfma_tflops", 0), ("bf16_mfma_tflops", 1)):
+        if lib.h2p_mfma(bf16, 20000 if not bf16 else 40000, 2, sink.data_ptr(), ctypes.byref(ms),
+                        ctypes.byref(fl)) == 0:
+            out[name] = round(fl.value / (ms.value * 1e-3) / 1e12, 1)
+    torch.cuda.synchronize()
+    return out
+
+
 def measured_copy_gbs(torch, nbytes: int = 4 << 30, reps: int = 5) -> float:
     """HBM bandwidth of a plain device-to-device copy (bytes read + written
     per second), the measured counterpart of the 8 TB/s datasheet figure."""
@@ -251,15 +282,35 @@ def stored_entries(buf) -> int:
     return int(r["U"].size + r["V"].size + r["E"].size + r["F"].size + r["S"].size + r["D"].size)
 
 
+def tree_rows(buf) -> int:
+    """Rows of the vector trees x^ and y^ for one vector: per node, the larger
+    of its level's row and column ranks."""
+    from h2gen import fmt
+    r = fmt.parse(buf)
+    lp, kr, kc = r["level_ptr"], r["krow"], r["kcol"]
+    return int(sum((lp[l + 1] - lp[l]) * max(kr[l], kc[l]) for l in range(len(kr))))
+
+
+def hbm_roofline(bytes_: float, t_ms: float, what: str) -> dict:
+    """Achieved rate of `bytes_` algorithmic bytes in t_ms against the HBM peak."""
+    achieved = bytes_ / (t_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": what,
+            "bytes_per_launch": bytes_, "ms_per_launch": round(t_ms, 4)}
+
+
 def bench_batch(args, torch):
     import h2gen
     from paper_2109_05451_amd import H2Batch
     specs = batch_ops(args.batch_count)
     t0 = time.perf_counter()
-    bufs, flops = [], 0.0
+    bufs, flops, bytes_ = [], 0.0, 0.0
     for sp in specs:
         b = h2gen.build(h2gen.points(sp["n"], 2, sp["seed_pts"]), sp["leaf"], sp["p"], 0.7, "exp", sp["ell"])
-        flops += 2.0 * sp["nv"] * stored_entries(b.array) + sp["n"] * sp["nv"]
+        ent = stored_entries(b.array)
+        flops += 2.0 * sp["nv"] * ent + sp["n"] * sp["nv"]
+        # each stored entry read once; X read, Y written, x^ and y^ written and read once
+        bytes_ += 8.0 * ent + 8.0 * sp["nv"] * (2 * sp["n"] + 4 * tree_rows(b.array))
         bufs.append(b)
     print(f"# built {len(bufs)} operators in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -299,7 +350,9 @@ def bench_batch(args, torch):
                                    "Chebyshev p in {4,5,6}, exp(-r/l) l~U[0.05,0.2], eta 0.7, nv~U{1..32}; "
                                    "merged level by level into single launches, autotuned, HIP graph replay",
                        "operators": len(specs), "total_n": info["total_n"], "launches_per_call": info["launches"],
-                       "flops_per_call": flops},
+                       "flops_per_call": flops, "alg_bytes_per_call": bytes_},
+            "roofline": hbm_roofline(bytes_, t_ms, "whole batched call (every merged launch; HBM-bound at about "
+                                                   f"{flops / bytes_:.1f} flop/B)"),
             "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
                            "p99": round(float(np.percentile(per, 99)), 4)}}
 
@@ -326,7 +379,7 @@ def bench_serving(args, torch):
     rng = np.random.default_rng(5000)
     nvs = [1, 4, 16, 64]
     pool = {(i, v): torch.randn(v, ops[i].n, dtype=torch.float64, device="cuda").t() for i in range(8) for v in nvs}
-    server = H2Server(ops, slots=4, budget_bytes=8 << 30, max_fuse_nv=64)
+    server = H2Server(ops, slots=4, budget_bytes=0, max_fuse_nv=64)  # a quarter of the free HBM
     torch.cuda.synchronize()
 
     def draw():
@@ -384,9 +437,13 @@ def bench_serving(args, torch):
             "gflops": round(served_flops / wall / 1e9, 2),
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                            "p99": round(float(np.percentile(lat, 99)), 3), "mean": round(float(lat.mean()), 3)},
+            "roofline": hbm_roofline(st["alg_bytes"] - st0["alg_bytes"], 1e3 * wall,
+                                     "every fused call issued during the timed arrivals (algorithmic bytes at each "
+                                     "call's precision over the wall time, idle gaps included)"),
             "server": {"calls": st["calls"] - st0["calls"], "requests": st["completed"] - st0["completed"],
                        "vectors_per_call": round((st["vectors"] - st0["vectors"]) / max(1, st["calls"] - st0["calls"]), 2),
-                       "max_inflight_calls": st["max_inflight_calls"]}}
+                       "max_inflight_calls": st["max_inflight_calls"], "budget_bytes": st["budget_bytes"],
+                       "hbm_free_at_create": st["hbm_free_at_create"]}}
 
 
 def bench_compress(args, torch):
@@ -512,7 +569,9 @@ def main():
         print(json.dumps(bench_compress(args, torch)), flush=True)
         return
     copy_gbs = measured_copy_gbs(torch)
-    print(f"# measured device copy: {copy_gbs:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
+    peaks = measured_peaks(torch)
+    print(f"# measured device copy: {copy_gbs:.0f} GB/s (read + write); peaks {peaks}", file=sys.stderr,
+          flush=True)
     import h2gen
     cfg = h2gen.CONFIGS[args.config]
     nv = args.nv or cfg["nv"][0]
@@ -547,9 +606,10 @@ def main():
     else:
         achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "peak_measured_copy": round(copy_gbs, 1),
-                    "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        if peaks and peaks.get("hbm_read_gbs"):
+            roofline.update({"peak_measured_read": peaks["hbm_read_gbs"],
+                             "frac_of_measured_read": round(achieved / peaks["hbm_read_gbs"], 4)})
     roofline.update({"traffic": measured_traffic(args.config, nv, dom),
                      "kernel": f"{kname} ({dom} rows)",
                      "bytes_per_launch": dom_bytes, "flops_per_launch": dom_flops,
@@ -574,6 +634,8 @@ def main():
                        "samples": int(r.get("lat_samples", len(r["per_call"]))),
                        "launches_per_product": r.get("launches")},
         "hbm_copy_measured_gbs": round(copy_gbs, 1),
+        "measured_peaks": dict(peaks or {}, datasheet={"hbm_gbs": HBM_PEAK_GBS, "fp64_tflops": FP64_PEAK_TFLOPS,
+                                                        "bf16_tflops": BF16_PEAK_TFLOPS}),
         "variants": [variant_record(wname, wst, v, prec, res)
                      for wname, _, wst, _, wres in work for (v, prec), res in wres.items()
                      if (wname, v, prec) != (args.config, nv, "fp64")],
