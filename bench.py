@@ -144,7 +144,7 @@ def measured_peaks(torch) -> dict:
     del buf
     fl = ctypes.c_double()
     for name, bf16 in (("fp64_mfma_tflops", 0), ("bf16_mfma_tflops", 1)):
-        if lib.h2p_mfma(bf16, 20000 if not bf16 else 40000, 2, sink.data_ptr(), ctypes.byref(ms),
+        if lib.h2p_mfma(bf16, 5000 if not bf16 else 10000, 8, sink.data_ptr(), ctypes.byref(ms),
                         ctypes.byref(fl)) == 0:
             out[name] = round(fl.value / (ms.value * 1e-3) / 1e12, 1)
     torch.cuda.synchronize()
@@ -314,7 +314,7 @@ def bench_batch(args, torch):
         bufs.append(b)
     print(f"# built {len(bufs)} operators in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    batch = H2Batch([b.array for b in bufs], nv_max=32)
+    batch = H2Batch([b.array for b in bufs], nv_max=[sp["nv"] for sp in specs])  # each operator's own width
     info = batch.info()
     for b in bufs:
         b.free()
@@ -348,7 +348,8 @@ def bench_batch(args, torch):
             "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"{len(specs)} independent 2D operators, N=round(2^U(12,16)), leaf U{{32..64}}, "
                                    "Chebyshev p in {4,5,6}, exp(-r/l) l~U[0.05,0.2], eta 0.7, nv~U{1..32}; "
-                                   "merged level by level into single launches, autotuned, HIP graph replay",
+                                   "merged level by level into single launches per vector width (16 or 32), "
+                                   "autotuned, HIP graph replay",
                        "operators": len(specs), "total_n": info["total_n"], "launches_per_call": info["launches"],
                        "flops_per_call": flops, "alg_bytes_per_call": bytes_},
             "roofline": hbm_roofline(bytes_, t_ms, "whole batched call (every merged launch; HBM-bound at about "

@@ -318,14 +318,15 @@ int h2_free(h2_handle h);
  * the coupling products of every level of every operator in one launch
  * (Algorithm 4), the downsweep aligned by depth from the root (Algorithm 6),
  * the dense leaf rows (second stream) and the leaf expansion.  Products run
- * on the FP64 MFMA row kernels with nv_max vectors per row (padding vectors
- * are zero); op 'N' only. */
+ * on the FP64 MFMA row kernels with nv_max vectors per row, rounded up to 16
+ * (padding vectors are zero); op 'N' only. */
 typedef struct h2_batch_s* h2_batch;
 
 /* One operator's product in a batched call:
  * Y <- alpha * A_i * X + beta * Y, X and Y device pointers, column-major
- * n_i x nv in original point order (leading dimensions >= n_i).  nv == 0
- * skips the operator; alpha == 0 does not read X; beta == 0 does not read Y. */
+ * n_i x nv in original point order (leading dimensions >= n_i), nv at most
+ * the operator's nv_max.  nv == 0 skips the operator; alpha == 0 does not
+ * read X; beta == 0 does not read Y. */
 typedef struct {
   const double* X;
   int64_t ldx;
@@ -342,6 +343,14 @@ typedef struct {
  * and the merged schedules.  Errors: as h2_load_mem. */
 int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, int64_t nv_max, int device,
                   h2_batch* out);
+
+/* As h2_batch_load with a vector bound per operator: operator i's calls
+ * carry at most nv_max[i] (1..64) vectors.  Operators are grouped by
+ * nv_max rounded up to 16 (the matrix-core tile width): each group has its
+ * own workspace and merged launches, so an operator bounded by 16 vectors
+ * costs the work of 16, not of the batch's widest operator. */
+int h2_batch_load_ex(const void* const* bufs, const size_t* lens, int64_t count, const int64_t* nv_max, int device,
+                     h2_batch* out);
 
 /* All products of one call: items[i] belongs to operator i (count items).
  * Asynchronous on `stream`; the items array is copied during the call.

@@ -21,7 +21,7 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_gemv_noalloc", "h2_prepare", "h2_reserve", "h2_tune",
            "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set", "h2_set_dense_grid", "h2_set_sweeps",
-           "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_gemv",
+           "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_load_ex", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
 
@@ -143,6 +143,9 @@ def load_library(path: str = LIB_PATH):
     lib.h2_batch_load.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t), i64, i64, ci,
                                   ctypes.POINTER(vp)]
     lib.h2_batch_load.restype = ci
+    lib.h2_batch_load_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t), i64, ctypes.POINTER(i64),
+                                     ci, ctypes.POINTER(vp)]
+    lib.h2_batch_load_ex.restype = ci
     lib.h2_batch_gemv.argtypes = [vp, ctypes.POINTER(H2BatchItem), vp]
     lib.h2_batch_gemv.restype = ci
     lib.h2_batch_tune.argtypes = [vp, ctypes.POINTER(H2BatchItem), vp]
@@ -348,22 +351,28 @@ class H2Operator:
 class H2Batch:
     """Several operators applied together by merged launches (op 'N', FP64).
 
-    ``bufs``: list of uint8 buffers holding serialized representations.
-    ``gemv(Xs, Ys, nvs, alphas, betas)`` takes per-operator device tensors
-    (column-major n_i x nv_i) and computes Y_i <- alpha_i A_i X_i + beta_i Y_i.
+    ``bufs``: list of uint8 buffers holding serialized representations;
+    ``nv_max``: the largest vector count of any call, one for all operators
+    or one per operator.  ``gemv(Xs, Ys, nvs, alphas, betas)`` takes
+    per-operator device tensors (column-major n_i x nv_i) and computes
+    Y_i <- alpha_i A_i X_i + beta_i Y_i.
     """
 
-    def __init__(self, bufs, nv_max: int, device: int = 0):
+    def __init__(self, bufs, nv_max, device: int = 0):
         lib = load_library()
         self._keep = [np.ascontiguousarray(np.asarray(b).view(np.uint8).ravel()) for b in bufs]
         ptrs = (ctypes.c_void_p * len(bufs))(*[b.ctypes.data for b in self._keep])
         lens = (ctypes.c_size_t * len(bufs))(*[b.size for b in self._keep])
+        nvm = [int(nv_max)] * len(bufs) if np.isscalar(nv_max) else [int(v) for v in nv_max]
+        if len(nvm) != len(bufs):
+            raise ValueError("one nv_max per operator")
         h = ctypes.c_void_p()
-        _check(lib.h2_batch_load(ptrs, lens, len(bufs), nv_max, device, ctypes.byref(h)))
+        _check(lib.h2_batch_load_ex(ptrs, lens, len(bufs), (ctypes.c_int64 * len(nvm))(*nvm), device,
+                                    ctypes.byref(h)))
         self._keep = None  # only read during the load
         self._h = h
         self.count = len(bufs)
-        self.nv_max = nv_max
+        self.nv_max = nvm
         self.device = device
 
     def close(self):

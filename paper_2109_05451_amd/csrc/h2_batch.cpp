@@ -7,8 +7,15 @@
 // transfer level q_i - h + 1 of every operator with q_i >= h (aligned by
 // height from the leaves), downsweep launch l holds level l of every operator
 // with q_i >= l (aligned by depth from the root).
+//
+// Operators are grouped by vector width: operator i's rows carry
+// nvp_i = nv_max_i rounded up to 16 vectors (the MFMA tile width), so an
+// operator that never takes more than 16 vectors does not pay for 32.  Each
+// width has its own workspace arena and its own merged launches; the launches
+// of the groups follow each other, interleaved level by level.
 #include <algorithm>
 #include <array>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -40,22 +47,31 @@ struct DevGuard {
   }
 };
 
+// The operators of one vector width: their workspace arena (row-major, nvp
+// doubles per row), merged launches and permutation tiles.
+struct Group {
+  int nvp = 16;
+  double* d_ws = nullptr;
+  int64_t ws_rows = 0;
+  std::vector<Launch> up, couple, down, dense, out;  // up[h] / down[d]: merged level h / d (may be absent)
+  std::vector<int64_t> up_level, down_level;         // the merged level of each launch
+  int32_t *d_tile_op = nullptr, *d_tile_j0 = nullptr;
+  int64_t ntiles = 0;
+};
+
 }  // namespace
 }  // namespace h2
 
 struct h2_batch_s {
   int device = 0;
-  int64_t count = 0, nvp = 16, nv_max = 1, nmax = 0, total_n = 0;
+  int64_t count = 0, nmax = 0, total_n = 0, maxq = 0;
   double flops_per_vector = 0.0;
-  std::vector<int64_t> n, pinv_off, xt_row, zn_row;
+  std::vector<int64_t> n, nv_max, pinv_off, xt_row, zn_row;
   double* d_mat = nullptr;
   double* d_trans = nullptr;
-  double* d_ws = nullptr;
   int32_t* d_pinv = nullptr;
-  int32_t *d_tile_op = nullptr, *d_tile_j0 = nullptr;  // permutation tiles (operator, first row)
-  int64_t ntiles = 0;
   h2::RowTables rt;
-  std::vector<h2::Launch> up, couple, down, dense, out;
+  std::vector<h2::Group> groups;
   h2::BatchItem* h_items = nullptr;  // pinned
   h2::BatchItem* d_items = nullptr;
   hipStream_t side = nullptr;
@@ -71,7 +87,10 @@ namespace {
 
 void free_batch(h2_batch_s* b) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
-  F(b->d_mat); F(b->d_trans); F(b->d_ws); F(b->d_pinv); F(b->d_items); F(b->d_tile_op); F(b->d_tile_j0);
+  F(b->d_mat); F(b->d_trans); F(b->d_pinv); F(b->d_items);
+  for (Group& g : b->groups) {
+    F(g.d_ws); F(g.d_tile_op); F(g.d_tile_j0);
+  }
   F(b->rt.d_rows); F(b->rt.d_colend); F(b->rt.d_in_off);
   if (b->h_items) (void)hipHostFree(b->h_items);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -81,9 +100,9 @@ void free_batch(h2_batch_s* b) {
   if (b->side) (void)hipStreamDestroy(b->side);
 }
 
-void add_phase(h2_batch_s* b, std::vector<RowSpec>& rows, int arr, int mode, bool sort, bool lowrank,
+bool add_phase(h2_batch_s* b, std::vector<RowSpec>& rows, int arr, int mode, bool sort, bool lowrank,
                std::vector<Launch>& dst) {
-  if (rows.empty()) return;
+  if (rows.empty()) return false;
   if (sort)
     std::stable_sort(rows.begin(), rows.end(),
                      [](const RowSpec& x, const RowSpec& y) { return row_work(x) > row_work(y); });
@@ -99,6 +118,7 @@ void add_phase(h2_batch_s* b, std::vector<RowSpec>& rows, int arr, int mode, boo
   }
   L.row_count = (int64_t)b->rt.rows.size() - L.row_begin;
   dst.push_back(L);
+  return true;
 }
 
 int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_batch_s* b) {
@@ -112,13 +132,27 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
     }
     if ((rc = make_layout(P[i], &lay[i])) != H2_OK) return rc;
   }
-  // arena offsets
+  // groups by vector width
+  std::map<int, size_t> gidx;
+  std::vector<size_t> op_group(count);
+  for (int64_t i = 0; i < count; ++i) {
+    const int nvp = (int)((b->nv_max[i] + 15) / 16 * 16);
+    auto it = gidx.find(nvp);
+    if (it == gidx.end()) {
+      it = gidx.emplace(nvp, b->groups.size()).first;
+      b->groups.emplace_back();
+      b->groups.back().nvp = nvp;
+    }
+    op_group[i] = it->second;
+  }
+  // arena offsets: matrix data and transposed bases shared, workspace rows per group
   auto up32 = [](int64_t x) { return (x + 31) / 32 * 32; };
   std::vector<RowBases> base(count);
-  int64_t mat = 0, trans = 0, row = 0, pin = 0;
+  int64_t mat = 0, trans = 0, pin = 0;
   b->n.resize(count); b->pinv_off.resize(count); b->xt_row.resize(count); b->zn_row.resize(count);
   for (int64_t i = 0; i < count; ++i) {
     RowBases& B = base[i];
+    int64_t& row = b->groups[op_group[i]].ws_rows;
     B.mat = mat;
     B.trans = trans;
     mat = up32(mat + lay[i].nmat);
@@ -135,34 +169,39 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
     b->nmax = std::max(b->nmax, P[i].n);
     b->total_n += P[i].n;
     const int64_t q = P[i].q;
+    b->maxq = std::max(b->maxq, q);
     b->flops_per_vector += 2.0 * (double)(P[i].n * P[i].krow[q] + P[i].n * P[i].kcol[q] + P[i].ebase[q + 1] +
                                           P[i].fbase[q + 1] + P[i].sdat[q + 1] + P[i].ddat[P[i].ndense]);
   }
-  // rows of every operator, merged level by level
-  int64_t maxq = 0;
-  for (int64_t i = 0; i < count; ++i) maxq = std::max(maxq, P[i].q);
-  std::vector<std::vector<RowSpec>> up(maxq + 1), down(maxq);
-  std::vector<RowSpec> couple, dense, outr;
-  for (int64_t i = 0; i < count; ++i) {
-    RowsN R;
-    emit_rows_N(lay[i], base[i], &R);
-    for (size_t h = 0; h < R.up.size(); ++h) up[h].insert(up[h].end(), R.up[h].begin(), R.up[h].end());
-    for (size_t d = 0; d < R.down.size(); ++d) down[d].insert(down[d].end(), R.down[d].begin(), R.down[d].end());
-    couple.insert(couple.end(), R.couple.begin(), R.couple.end());
-    dense.insert(dense.end(), R.dense.begin(), R.dense.end());
-    outr.insert(outr.end(), R.out.begin(), R.out.end());
+  // rows of every operator, merged level by level within each group
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    Group& G = b->groups[gi];
+    std::vector<std::vector<RowSpec>> up(b->maxq + 1), down(b->maxq);
+    std::vector<RowSpec> couple, dense, outr;
+    for (int64_t i = 0; i < count; ++i) {
+      if (op_group[i] != gi) continue;
+      RowsN R;
+      emit_rows_N(lay[i], base[i], &R);
+      for (size_t h = 0; h < R.up.size(); ++h) up[h].insert(up[h].end(), R.up[h].begin(), R.up[h].end());
+      for (size_t d = 0; d < R.down.size(); ++d) down[d].insert(down[d].end(), R.down[d].begin(), R.down[d].end());
+      couple.insert(couple.end(), R.couple.begin(), R.couple.end());
+      dense.insert(dense.end(), R.dense.begin(), R.dense.end());
+      outr.insert(outr.end(), R.out.begin(), R.out.end());
+    }
+    for (const auto* v : {&couple, &dense})
+      for (const RowSpec& r : *v)
+        if ((int64_t)r.blks.size() > kNbMax) {
+          set_error("batch: a row with more than 512 blocks");
+          return H2_EUNSUPPORTED;
+        }
+    for (int64_t h = 0; h <= b->maxq; ++h)
+      if (add_phase(b, up[h], ARR_TRANS, MODE_STORE, false, true, G.up)) G.up_level.push_back(h);
+    add_phase(b, couple, ARR_MAT, MODE_STORE, true, true, G.couple);
+    for (int64_t d = 0; d < b->maxq; ++d)
+      if (add_phase(b, down[d], ARR_MAT, MODE_ACCUM, false, true, G.down)) G.down_level.push_back(d);
+    add_phase(b, dense, ARR_MAT, MODE_STORE, true, false, G.dense);
+    add_phase(b, outr, ARR_MAT, MODE_ACCUM, false, true, G.out);
   }
-  for (const auto* v : {&couple, &dense})
-    for (const RowSpec& r : *v)
-      if ((int64_t)r.blks.size() > kNbMax) {
-        set_error("batch: a row with more than 512 blocks");
-        return H2_EUNSUPPORTED;
-      }
-  for (int64_t h = 0; h <= maxq; ++h) add_phase(b, up[h], ARR_TRANS, MODE_STORE, false, true, b->up);
-  add_phase(b, couple, ARR_MAT, MODE_STORE, true, true, b->couple);
-  for (int64_t d = 0; d < maxq; ++d) add_phase(b, down[d], ARR_MAT, MODE_ACCUM, false, true, b->down);
-  add_phase(b, dense, ARR_MAT, MODE_STORE, true, false, b->dense);
-  add_phase(b, outr, ARR_MAT, MODE_ACCUM, false, true, b->out);
 
   // device arena: matrix data, transposed bases, inverse permutations
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_mat), sizeof(double) * std::max<int64_t>(mat, 1)), "hipMalloc(arena)");
@@ -184,14 +223,6 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   }
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_pinv), sizeof(int32_t) * pinv.size()), "hipMalloc(pinv)");
   HIP_TRYB(hipMemcpy(b->d_pinv, pinv.data(), sizeof(int32_t) * pinv.size(), hipMemcpyHostToDevice), "hipMemcpy");
-  // permutation tiles: kPermTile original rows of one operator each
-  std::vector<int32_t> tile_op, tile_j0;
-  for (int64_t i = 0; i < count; ++i)
-    for (int64_t j0 = 0; j0 < P[i].n; j0 += kPermTile) {
-      tile_op.push_back((int32_t)i);
-      tile_j0.push_back((int32_t)j0);
-    }
-  b->ntiles = (int64_t)tile_op.size();
   // schedules
   auto up_tab = [&](auto& v, auto** d) -> int {
     if (v.empty()) return H2_OK;
@@ -201,13 +232,25 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   };
   int rc;
   if ((rc = up_tab(b->rt.rows, &b->rt.d_rows)) || (rc = up_tab(b->rt.colend, &b->rt.d_colend)) ||
-      (rc = up_tab(b->rt.in_off, &b->rt.d_in_off)) || (rc = up_tab(tile_op, &b->d_tile_op)) ||
-      (rc = up_tab(tile_j0, &b->d_tile_j0)))
+      (rc = up_tab(b->rt.in_off, &b->rt.d_in_off)))
     return rc;
-  // workspace (row-major, nvp per row), zeroed once
-  HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_ws), sizeof(double) * std::max<int64_t>(row, 1) * b->nvp),
-           "hipMalloc(workspace)");
-  HIP_TRYB(hipMemset(b->d_ws, 0, sizeof(double) * std::max<int64_t>(row, 1) * b->nvp), "hipMemset(workspace)");
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    Group& G = b->groups[gi];
+    // permutation tiles: kPermTile original rows of one operator each
+    std::vector<int32_t> tile_op, tile_j0;
+    for (int64_t i = 0; i < count; ++i)
+      if (op_group[i] == gi)
+        for (int64_t j0 = 0; j0 < P[i].n; j0 += kPermTile) {
+          tile_op.push_back((int32_t)i);
+          tile_j0.push_back((int32_t)j0);
+        }
+    G.ntiles = (int64_t)tile_op.size();
+    if ((rc = up_tab(tile_op, &G.d_tile_op)) || (rc = up_tab(tile_j0, &G.d_tile_j0))) return rc;
+    // workspace (row-major, nvp per row), zeroed once
+    const size_t wsb = sizeof(double) * std::max<int64_t>(G.ws_rows, 1) * G.nvp;
+    HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&G.d_ws), wsb), "hipMalloc(workspace)");
+    HIP_TRYB(hipMemset(G.d_ws, 0, wsb), "hipMemset(workspace)");
+  }
   HIP_TRYB(hipHostMalloc(reinterpret_cast<void**>(&b->h_items), sizeof(BatchItem) * count, hipHostMallocDefault),
            "hipHostMalloc(items)");
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_items), sizeof(BatchItem) * count), "hipMalloc(items)");
@@ -219,41 +262,55 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   return H2_OK;
 }
 
-int run_blaunch(h2_batch_s* b, const Launch& L, hipStream_t s) {
+int run_blaunch(h2_batch_s* b, const Group& G, const Launch& L, hipStream_t s) {
   const double* data = L.arr == ARR_TRANS ? b->d_trans : b->d_mat;
   if (L.kc == kWaveRows && L.max_rows <= 64) {
     const hipError_t e = launch_wave_rows<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend,
-                                                  b->rt.d_in_off, data, b->d_ws, b->d_ws, (int)b->nvp, L.mode,
+                                                  b->rt.d_in_off, data, G.d_ws, G.d_ws, G.nvp, L.mode,
                                                   L.max_rows, s, L.grid);
     if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
     return H2_OK;
   }
   hipError_t e = launch_rows_mfma<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend, b->rt.d_in_off,
-                                          data, b->d_ws, b->d_ws, (int)b->nvp, L.mode, L.max_rows, s, L.kc, L.grid);
+                                          data, G.d_ws, G.d_ws, G.nvp, L.mode, L.max_rows, s, L.kc, L.grid);
   if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
+  return H2_OK;
+}
+
+// Launches of one phase of every group, merged level `lev` (or all, lev < 0).
+int run_phase(h2_batch_s* b, std::vector<Launch> Group::*ph, const std::vector<int64_t> Group::*lv, int64_t lev,
+              hipStream_t s) {
+  int rc;
+  for (const Group& G : b->groups) {
+    const std::vector<Launch>& v = G.*ph;
+    for (size_t k = 0; k < v.size(); ++k) {
+      if (lv && (G.*lv)[k] != lev) continue;
+      if ((rc = run_blaunch(b, G, v[k], s))) return rc;
+    }
+  }
   return H2_OK;
 }
 
 // The launch sequence after the items are on the device.
 int batch_sequence(h2_batch_s* b, hipStream_t s) {
   int rc;
-  HIP_TRYB(launch_batch_permute(b->d_items, b->d_tile_op, b->d_tile_j0, b->ntiles, b->d_pinv, b->d_ws, (int)b->nvp,
-                                false, s),
-           "batch permute");
+  for (const Group& G : b->groups)
+    HIP_TRYB(launch_batch_permute(b->d_items, G.d_tile_op, G.d_tile_j0, G.ntiles, b->d_pinv, G.d_ws, G.nvp, false, s),
+             "batch permute");
   HIP_TRYB(hipEventRecord(b->ev_fork, s), "hipEventRecord");
   HIP_TRYB(hipStreamWaitEvent(b->side, b->ev_fork, 0), "hipStreamWaitEvent");
-  for (const Launch& L : b->dense)
-    if ((rc = run_blaunch(b, L, b->side))) return rc;
+  if ((rc = run_phase(b, &Group::dense, nullptr, -1, b->side))) return rc;
   HIP_TRYB(hipEventRecord(b->ev_join, b->side), "hipEventRecord");
-  for (const auto* v : {&b->up, &b->couple, &b->down})
-    for (const Launch& L : *v)
-      if ((rc = run_blaunch(b, L, s))) return rc;
+  for (int64_t h = 0; h <= b->maxq; ++h)
+    if ((rc = run_phase(b, &Group::up, &Group::up_level, h, s))) return rc;
+  if ((rc = run_phase(b, &Group::couple, nullptr, -1, s))) return rc;
+  for (int64_t d = 0; d < b->maxq; ++d)
+    if ((rc = run_phase(b, &Group::down, &Group::down_level, d, s))) return rc;
   HIP_TRYB(hipStreamWaitEvent(s, b->ev_join, 0), "hipStreamWaitEvent");
-  for (const Launch& L : b->out)
-    if ((rc = run_blaunch(b, L, s))) return rc;
-  HIP_TRYB(launch_batch_permute(b->d_items, b->d_tile_op, b->d_tile_j0, b->ntiles, b->d_pinv, b->d_ws, (int)b->nvp,
-                                true, s),
-           "batch permute out");
+  if ((rc = run_phase(b, &Group::out, nullptr, -1, s))) return rc;
+  for (const Group& G : b->groups)
+    HIP_TRYB(launch_batch_permute(b->d_items, G.d_tile_op, G.d_tile_j0, G.ntiles, b->d_pinv, G.d_ws, G.nvp, true, s),
+             "batch permute out");
   return H2_OK;
 }
 
@@ -262,8 +319,8 @@ int fill_items(h2_batch_s* b, const h2_batch_item* items) {
   if (b->items_pending) HIP_TRYB(hipEventSynchronize(b->ev_items), "hipEventSynchronize(items)");
   for (int64_t i = 0; i < b->count; ++i) {
     const h2_batch_item& it = items[i];
-    if (it.nv < 0 || it.nv > b->nv_max) {
-      set_error("batch item " + std::to_string(i) + ": nv outside [0, nv_max]");
+    if (it.nv < 0 || it.nv > b->nv_max[i]) {
+      set_error("batch item " + std::to_string(i) + ": nv outside [0, the operator's nv_max]");
       return H2_EINVAL;
     }
     if (it.nv > 0) {
@@ -280,6 +337,13 @@ int fill_items(h2_batch_s* b, const h2_batch_item* items) {
   return H2_OK;
 }
 
+int64_t launch_count(const h2_batch_s* b) {
+  int64_t l = 0;
+  for (const Group& G : b->groups)
+    l += 2 + (int64_t)(G.up.size() + G.couple.size() + G.down.size() + G.dense.size() + G.out.size());
+  return l;
+}
+
 }  // namespace
 }  // namespace h2
 
@@ -287,15 +351,20 @@ using namespace h2;
 
 extern "C" {
 
-int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, int64_t nv_max, int device,
-                  h2_batch* out) {
-  if (!out || !bufs || !lens || count < 1 || nv_max < 1 || nv_max > kPassVectorsMfma) {
+int h2_batch_load_ex(const void* const* bufs, const size_t* lens, int64_t count, const int64_t* nv_max, int device,
+                     h2_batch* out) {
+  if (!out || !bufs || !lens || !nv_max || count < 1) {
     set_error("h2_batch_load: bad arguments");
     return H2_EINVAL;
   }
   *out = nullptr;
-  for (int64_t i = 0; i < count; ++i)
+  for (int64_t i = 0; i < count; ++i) {
     if (!bufs[i]) { set_error("h2_batch_load: null buffer"); return H2_EINVAL; }
+    if (nv_max[i] < 1 || nv_max[i] > kPassVectorsMfma) {
+      set_error("h2_batch_load: nv_max of operator " + std::to_string(i) + " outside [1, 64]");
+      return H2_EINVAL;
+    }
+  }
   int ndev = 0;
   HIP_TRYB(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   if (device < 0 || device >= ndev) { set_error("device ordinal out of range"); return H2_EINVAL; }
@@ -305,10 +374,9 @@ int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, in
   if (!b) { set_error("out of host memory"); return H2_ENOMEM; }
   b->device = device;
   b->count = count;
-  b->nv_max = nv_max;
-  b->nvp = (nv_max + 15) / 16 * 16;
   int rc;
   try {
+    b->nv_max.assign(nv_max, nv_max + count);
     rc = batch_build(bufs, lens, count, b);
   } catch (const std::bad_alloc&) {
     set_error("out of host memory while building the batch");
@@ -322,6 +390,22 @@ int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, in
   }
   *out = b;
   return H2_OK;
+}
+
+int h2_batch_load(const void* const* bufs, const size_t* lens, int64_t count, int64_t nv_max, int device,
+                  h2_batch* out) {
+  if (count < 1) {
+    set_error("h2_batch_load: bad arguments");
+    return H2_EINVAL;
+  }
+  std::vector<int64_t> v;
+  try {
+    v.assign((size_t)count, nv_max);
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory");
+    return H2_ENOMEM;
+  }
+  return h2_batch_load_ex(bufs, lens, count, v.data(), device, out);
 }
 
 int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream) {
@@ -385,37 +469,38 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
   HIP_TRYB(hipEventCreate(&e1), "hipEventCreate");
   const int kcs[3] = {32, 64, kWaveRows};  // chunk widths of the LDS-staged kernel; a wave per row
   const int64_t grids[4] = {0, 1024, 2048, 4096};
-  for (auto* v : {&b->up, &b->couple, &b->down, &b->dense, &b->out})
-    for (Launch& L : *v) {
-      float best = 1e30f;
-      int best_kc = L.kc;
-      int64_t best_grid = L.grid;
-      for (int kc : kcs)
-        for (int64_t gsz : grids) {
-          if (gsz != 0 && gsz >= L.row_count) continue;
-          if (kc == kWaveRows && L.max_rows > 64) continue;
-          Launch T = L;
-          T.kc = kc;
-          T.grid = gsz;
-          float tsum = 0.0f;
-          for (int rep = 0; rep < 3; ++rep) {
-            HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
-            if ((rc = run_blaunch(b, T, s))) return rc;
-            HIP_TRYB(hipEventRecord(e1, s), "hipEventRecord");
-            HIP_TRYB(hipEventSynchronize(e1), "hipEventSynchronize");
-            float ms = 0.0f;
-            HIP_TRYB(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-            if (rep > 0) tsum += ms;  // first repetition warms up
+  for (Group& G : b->groups)
+    for (auto* v : {&G.up, &G.couple, &G.down, &G.dense, &G.out})
+      for (Launch& L : *v) {
+        float best = 1e30f;
+        int best_kc = L.kc;
+        int64_t best_grid = L.grid;
+        for (int kc : kcs)
+          for (int64_t gsz : grids) {
+            if (gsz != 0 && gsz >= L.row_count) continue;
+            if (kc == kWaveRows && L.max_rows > 64) continue;
+            Launch T = L;
+            T.kc = kc;
+            T.grid = gsz;
+            float tsum = 0.0f;
+            for (int rep = 0; rep < 3; ++rep) {
+              HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
+              if ((rc = run_blaunch(b, G, T, s))) return rc;
+              HIP_TRYB(hipEventRecord(e1, s), "hipEventRecord");
+              HIP_TRYB(hipEventSynchronize(e1), "hipEventSynchronize");
+              float ms = 0.0f;
+              HIP_TRYB(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+              if (rep > 0) tsum += ms;  // first repetition warms up
+            }
+            if (tsum < best) {
+              best = tsum;
+              best_kc = kc;
+              best_grid = gsz;
+            }
           }
-          if (tsum < best) {
-            best = tsum;
-            best_kc = kc;
-            best_grid = gsz;
-          }
-        }
-      L.kc = best_kc;
-      L.grid = best_grid;
-    }
+        L.kc = best_kc;
+        L.grid = best_grid;
+      }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->use_graph = graph_was;
@@ -436,8 +521,7 @@ int h2_batch_info(h2_batch b, int64_t* count, int64_t* total_n, double* flops_pe
   if (count) *count = b->count;
   if (total_n) *total_n = b->total_n;
   if (flops_per_vector) *flops_per_vector = b->flops_per_vector;
-  if (launches)
-    *launches = 2 + (int64_t)(b->up.size() + b->couple.size() + b->down.size() + b->dense.size() + b->out.size());
+  if (launches) *launches = launch_count(b);
   return H2_OK;
 }
 

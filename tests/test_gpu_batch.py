@@ -127,3 +127,44 @@ def test_batch_graph_replays():
             if y is not None:
                 assert np.array_equal(y.cpu().numpy(), eager[rep % 3][i]), (rep, i)
     batch.close()
+
+
+def test_batch_per_operator_widths():
+    """Operators bounded by 4, 16, 20, 40 and 64 vectors (three groups of
+    widths 16, 32 and 48 or 64): each group's merged launches and workspace
+    are separate; results are the oracle's (bit-exact on integer
+    representations), and a call above an operator's bound is refused."""
+    from paper_2109_05451_amd import H2Batch, H2Error
+    bufs, kinds = make_ops(3)
+    refs = [oracle.Oracle(b) for b in bufs]
+    bounds = [4, 16, 20, 40, 64, 16, 4, 33, 48, 64, 1]
+    batch = H2Batch(bufs, nv_max=bounds)
+    assert batch.info()["launches"] > 10
+    rng = np.random.default_rng(2)
+    for rep in range(2):
+        nvs = [int(rng.integers(0, b + 1)) for b in bounds]
+        Xs, Y0s, alphas, betas = [], [], [], []
+        for ref, kind, nv in zip(refs, kinds, nvs):
+            if kind == "int":
+                X = rng.integers(-2, 3, size=(ref.n, max(nv, 1))).astype(np.float64)
+                Y0 = rng.integers(-2, 3, size=(ref.n, max(nv, 1))).astype(np.float64)
+                a, b = 2.0, -1.0
+            else:
+                X = rng.standard_normal((ref.n, max(nv, 1)))
+                Y0 = rng.standard_normal((ref.n, max(nv, 1)))
+                a, b = 1.5, 0.0
+            Xs.append(X[:, :nv]); Y0s.append(Y0[:, :nv]); alphas.append(a); betas.append(b)
+        Xd = [to_dev(X) for X in Xs]
+        Yd = [to_dev(Y) for Y in Y0s]
+        if rep == 1:
+            batch.tune(Xd, [to_dev(Y) for Y in Y0s], alphas, betas)
+        batch.gemv(Xd, Yd, alphas, betas)
+        torch.cuda.synchronize()
+        check(refs, kinds, Xs, Y0s, nvs, alphas, betas, Yd)
+    # an item above its operator's bound
+    X = torch.zeros((refs[0].n, 5), dtype=torch.float64, device="cuda")
+    Xd = [X if i == 0 else None for i in range(len(refs))]
+    Yd = [torch.zeros_like(X) if i == 0 else None for i in range(len(refs))]
+    with pytest.raises(H2Error):
+        batch.gemv(Xd, Yd)
+    batch.close()

@@ -1,7 +1,8 @@
 """The batched workload at its own scale, as bench.py runs it: 256 independent
 2D operators, N = round(2^U(12,16)), leaf U{32..64}, Chebyshev p in {4,5,6},
-exp(-r/l) with l ~ U[0.05, 0.2], eta 0.7, nv ~ U{1..32}, merged level by
-level, autotuned, replayed from a captured HIP graph.  For every operator,
+exp(-r/l) with l ~ U[0.05, 0.2], eta 0.7, nv ~ U{1..32} (each operator's
+bound, so two vector widths: 16 and 32), merged level by level, autotuned,
+replayed from a captured HIP graph.  For every operator,
 sampled output rows (both ends and six seeded ones) of every vector are
 compared with the oracle's rows of that operator alone, computed one by one
 (h2o_gemv_rows), to the FP64 bar 1e-12 * B; every output is finite."""
@@ -21,7 +22,7 @@ def test_256_operators_every_operator_sampled_rows():
     specs = bench.batch_ops(256)
     bufs = [h2gen.build(h2gen.points(sp["n"], 2, sp["seed_pts"]), sp["leaf"], sp["p"], 0.7, "exp", sp["ell"])
             for sp in specs]
-    batch = H2Batch([b.array for b in bufs], nv_max=32)
+    batch = H2Batch([b.array for b in bufs], nv_max=[sp["nv"] for sp in specs])
     assert batch.info()["count"] == 256
     Xh = [h2gen.vectors(sp["n"], sp["nv"], sp["seed_vec"]) for sp in specs]
     Xs = [torch.from_numpy(np.asfortranarray(x)).cuda() for x in Xh]
