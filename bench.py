@@ -32,21 +32,36 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector and matrix, datasheet
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, datasheet (no sparsity)
 
 
-def measured_traffic(config: str, nv: int, phase: str):
+KERNEL_SOURCES = ("h2_kernels.hip", "h2_tree_kernels.hip")
+
+
+def kernel_source_md5() -> str:
+    """md5 of the kernel sources (in KERNEL_SOURCES order) that the profile
+    summaries record; None if one is missing."""
+    import hashlib
+    m = hashlib.md5()
+    for f in KERNEL_SOURCES:
+        path = os.path.join(ROOT, "paper_2109_05451_amd", "csrc", f)
+        if not os.path.exists(path):
+            return None
+        m.update(open(path, "rb").read())
+    return m.hexdigest()
+
+
+def measured_traffic(config: str, nv: int, phase: str, precision: str = "fp64"):
     """HBM bytes per launch of the dominant kernel (the launch of ``phase`` rows)
     from the committed rocprofv3 summary (FETCH_SIZE x calibration + WRITE_SIZE),
-    or None when there is no summary for this workload and phase or the kernel
-    source changed since it was taken."""
-    import hashlib
+    or None when there is no summary for this workload, precision and phase or
+    the kernel sources changed since it was taken."""
     import re
-    path = os.path.join(ROOT, "profiles", f"k_rows_{config}_nv{nv}.md")
-    src = os.path.join(ROOT, "paper_2109_05451_amd", "csrc", "h2_kernels.hip")
-    if not os.path.exists(path) or not os.path.exists(src):
+    suffix = "" if precision == "fp64" else "_" + precision
+    path = os.path.join(ROOT, "profiles", f"k_rows_{config}_nv{nv}{suffix}.md")
+    if not os.path.exists(path):
         return None
     text = open(path).read()
     m5 = re.search(r"kernel_source_md5: `([0-9a-f]+)`", text)
     tb = re.search(r"traffic_bytes_per_launch \(" + phase + r" rows\): ([0-9.eE+]+)", text)
-    if not m5 or not tb or m5.group(1) != hashlib.md5(open(src, "rb").read()).hexdigest():
+    if not m5 or not tb or m5.group(1) != kernel_source_md5():
         return None
     return float(tb.group(1))
 
@@ -93,7 +108,7 @@ PEAK_TFLOPS = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16": BF16_
 ELEM_BYTES = {"fp64": 8.0, "fp32": 4.0, "bf16": 2.0}
 
 
-def coupling_roofline(st: dict, nv: int, precision: str, t_ms: float) -> dict:
+def coupling_roofline(st: dict, nv: int, precision: str, t_ms: float, config: str = None) -> dict:
     """Roofline of the coupling launch (all levels' S x^ in one launch, the
     largest single launch of every multi-vector run) at a precision: the
     stored blocks and the vector trees (x^ read, y^ written) at that
@@ -110,7 +125,8 @@ def coupling_roofline(st: dict, nv: int, precision: str, t_ms: float) -> dict:
         achieved = bytes_ / (t_ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     out.update({"frac": round(achieved / out["peak"], 4), "kernel": f"coupling rows ({precision}, nv={nv})",
-                "bytes_per_launch": bytes_, "flops_per_launch": flops, "ms_per_launch": round(t_ms, 4)})
+                "bytes_per_launch": bytes_, "flops_per_launch": flops, "ms_per_launch": round(t_ms, 4),
+                "traffic": measured_traffic(config, nv, "coupling", precision) if config else None})
     return out
 
 
@@ -703,7 +719,7 @@ def variant_record(name, st, v, prec, res) -> dict:
             "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
             "rel_err_vs_oracle": res.get("rel_err"), "max_err_over_B": res.get("err_over_B"),
             "finite": res["finite"], "p99_ms": round(res["p99"], 4),
-            "roofline": coupling_roofline(st, v, prec, res["prof"]["coupling"]),
+            "roofline": coupling_roofline(st, v, prec, res["prof"]["coupling"], name),
             "path_roofline": path_roofline(st, v, prec, res["t_ms"]),
             "phases_ms": res["prof"]}
 

@@ -104,11 +104,13 @@ typedef struct {
   double ms_permute;      /* input permutation into tree order */
   double ms_upsweep;      /* leaf products V^T x and transfer upsweep */
   double ms_coupling;     /* coupling products, all levels */
-  double ms_downsweep;    /* transfer downsweep */
+  double ms_downsweep;    /* transfer downsweep (on the multi-vector path, with the leaf
+                             expansion U y^, which runs beside the dense rows there) */
   double ms_dense;        /* dense near-field blocks: the sum of the durations of its two
                              halves on the side stream (the first runs beside the upsweep,
                              the second beside the downsweep and the leaf expansion) */
-  double ms_leaf_out;     /* leaf expansion U y^ and the alpha/beta update */
+  double ms_leaf_out;     /* leaf expansion U y^ and the alpha/beta update (the output
+                             permutation and update only, on the multi-vector path) */
   double ms_total;        /* first to last event of each call, summed */
 } h2_profile_t;
 
@@ -196,7 +198,10 @@ int h2_reserve(h2_handle h, int64_t nv_max);
  * workspace buffers, and the fastest is kept for later calls in that
  * precision (the dense rows, always FP64, keep theirs in the FP64 entry);
  * then the fused sweeps are timed against the tuned per-level sweeps and the
- * faster form is kept (h2_set_sweeps).
+ * faster form is kept (h2_set_sweeps), and three schedules of the dense rows
+ * on their second stream (halves beside the upsweep and the downsweep; the
+ * first half beside the coupling launch instead; both from the start) are
+ * timed on whole products (zeroed input) and the fastest is kept.
  * Results do not depend on the choice: every candidate sums each output in
  * the same order, so they are bitwise identical.  No-op for nv <= 4 outside
  * BF16 (the streaming kernel has nothing to tune).  Synchronous; must not run concurrently with other calls on the
@@ -258,7 +263,8 @@ int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
  * CU, 7 or 8 the same with 8 columns and five workgroups per CU (0-8 take
  * passes of 64 vectors, 1-8 rows of at most 64 outputs; other launches use
  * 64 columns), 9 for one wave per row with no LDS staging (rows of at most
- * 64 outputs, any pass width); grid = workgroups (0 = one per
+ * 64 outputs, any pass width), 10 the same with one wave per 16-vector tile
+ * (passes of 32 or 64 vectors); grid = workgroups (0 = one per
  * row); xcd != 0 for XCD-aware row ranges; tree_order != 0 for tree-ordered
  * coupling and dense rows.  Results do not change (same summation order).  For
  * reproducible timing and for tests.  Errors: H2_EINVAL. */
@@ -276,8 +282,9 @@ int h2_set_dense_grid(h2_handle h, int64_t workgroups);
 /* How the multi-vector path (op 'N', 64-vector passes or fewer, FP64 and
  * FP32) runs the upsweep, the downsweep and the leaf expansion: fused != 0
  * in a few launches in which each workgroup runs several levels of one
- * subtree (the default when every row has at most 64 outputs), 0 one launch
- * per level.  Results are bitwise the same; h2_tune keeps the faster.
+ * subtree (operators whose rows have at most 64 outputs), 0 one launch per
+ * level (the default).  Results are bitwise the same; h2_tune keeps the
+ * faster.
  * Errors: H2_EINVAL (null handle, precision other than FP64 or FP32),
  * H2_EUNSUPPORTED (fused asked for, but the operator has longer rows). */
 int h2_set_sweeps(h2_handle h, int prec, int fused);

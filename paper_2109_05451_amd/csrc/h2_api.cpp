@@ -555,8 +555,11 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, con
 // FP32: the low-rank launches read the FP32 copy of the data (the dense
 // phase never does); x32: a coupling launch that may gather x^ from its FP32
 // copy (w.xh32, converted from w.xh after the upsweep).
+// out_ptr: an output buffer in place of the launch's own (the multi-vector
+// leaf expansion into w.zx).
 int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Epilogue& ep, hipStream_t s,
-               int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64, bool x32 = false) {
+               int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64, bool x32 = false,
+               double* out_ptr = nullptr) {
   double* bufs[4] = {w.xt, w.xh, w.yh, w.zn};
   const bool lowp = prec == H2_PREC_FP32 && L.lowrank && L.kind != KIND_WIDE;
   if (prec == H2_PREC_BF16 && L.lowrank && nvp > 0) {
@@ -566,7 +569,8 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
     const bool in16 = L.in == BUF_XH, out16 = mode_override < 0 && L.out == BUF_XH;
     const hipError_t eb = launch_rows_mfma_bf16(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend,
                                                 h->rt.d_in_off, L.arr == ARR_TRANS ? h->d_trans16 : h->d_mat16,
-                                                bufs[L.in], in16, ld16, bufs[mode_override >= 0 ? BUF_ZN : L.out],
+                                                bufs[L.in], in16, ld16,
+                                                out_ptr ? out_ptr : bufs[mode_override >= 0 ? BUF_ZN : L.out],
                                                 out16, ld16, nvp, mode_override >= 0 ? mode_override : L.mode,
                                                 L.max_rows, s, L.gridp[H2_PREC_BF16], L.remapp[H2_PREC_BF16]);
     if (eb != hipSuccess) return hip_fail(eb, "kernel launch");
@@ -574,7 +578,7 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   }
   const double* data = L.arr == ARR_TRANS ? h->d_trans : h->d_mat;
   const float* data32 = L.arr == ARR_TRANS ? h->d_trans32 : h->d_mat32;
-  double* out = bufs[mode_override >= 0 ? BUF_ZN : L.out];
+  double* out = out_ptr ? out_ptr : bufs[mode_override >= 0 ? BUF_ZN : L.out];
   const int mode = mode_override >= 0 ? mode_override : L.mode;
   hipError_t e = hipSuccess;
   // the dense rows' grid on the multi-vector path: the tuned one, or the
@@ -582,11 +586,13 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   const int64_t grid_of = [&](int pi) {
     return (!L.lowrank && h->dense_grid_mv >= 0) ? h->dense_grid_mv : L.gridp[pi];
   }(lowp ? H2_PREC_FP32 : H2_PREC_FP64);
-  if (nvp > 0 && L.kcp[lowp ? H2_PREC_FP32 : H2_PREC_FP64] == kWaveRows && L.max_rows <= 64) {
+  const int kcw = L.kcp[lowp ? H2_PREC_FP32 : H2_PREC_FP64];
+  if (nvp > 0 && (kcw == kWaveRows || kcw == kWaveTiles) && L.max_rows <= 64) {
+    const bool narrow = kcw == kWaveTiles;
     e = lowp ? launch_wave_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of)
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow)
              : launch_wave_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of);
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow);
   } else if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
@@ -717,12 +723,20 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   if (nvp) HIP_TRY(launch_permute_in_rm(X, ldx, h->d_pinv, w.xt, h->n, nv, nvp, s), "permute");
   else HIP_TRY(launch_permute_in(X, ldx, h->d_perm, w.xt, h->n, nv, s), "permute");
   STEP(mark(1, s));
-  // dense near field on the side stream, concurrent with the low-rank phases
-  HIP_TRY(hipEventRecord(w.ev_fork, s), "hipEventRecord(fork)");
-  HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");
-  STEP(mark(5, w.side));
-  for (const Launch& L : dense1) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
-  STEP(mark(9, w.side));
+  // dense near field on the side stream, concurrent with the low-rank phases.
+  // Schedule (multi-vector path, per precision, h2_tune): 0 the first half
+  // beside the upsweep, the second beside the downsweep; 1 the first half
+  // beside the coupling launch instead; 2 both halves from the start.
+  const int sched = nvp > 0 && !trans ? h->sched[pidx] : 0;
+  auto fork_dense1 = [&]() -> int {
+    HIP_TRY(hipEventRecord(w.ev_fork, s), "hipEventRecord(fork)");
+    HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");
+    STEP(mark(5, w.side));
+    for (const Launch& L : dense1) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
+    STEP(mark(9, w.side));
+    return H2_OK;
+  };
+  if (sched != 1) STEP(fork_dense1());
   const bool fused = use_tree(h, w, trans, nvp, prec);
   if (fused) STEP(run_tree(h, w, h->tree_up, nvp, prec, s));
   else
@@ -730,24 +744,31 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
   const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
   if (x32) HIP_TRY(launch_to_f32(w.xh, w.xh32, h->H * (int64_t)nvp, s), "x^ to FP32");
+  if (sched == 1) STEP(fork_dense1());
   STEP(mark(2, s));
   for (const Launch& L : couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec, x32));
   STEP(mark(3, s));
   // second half of the dense rows, beside the downsweep and the leaf expansion
-  HIP_TRY(hipEventRecord(w.ev_mid, s), "hipEventRecord(mid)");
-  HIP_TRY(hipStreamWaitEvent(w.side, w.ev_mid, 0), "hipStreamWaitEvent(mid)");
+  if (sched != 2) {
+    HIP_TRY(hipEventRecord(w.ev_mid, s), "hipEventRecord(mid)");
+    HIP_TRY(hipStreamWaitEvent(w.side, w.ev_mid, 0), "hipStreamWaitEvent(mid)");
+  }
   STEP(mark(10, w.side));
   for (const Launch& L : dense2) STEP(run_launch(h, w, L, nv, ep, w.side, nvp));
   STEP(mark(6, w.side));
   HIP_TRY(hipEventRecord(w.ev_join, w.side), "hipEventRecord(join)");
-  // (the fused downsweep ends with the leaf expansion into w.zx, beside the dense rows)
+  // Multi-vector path: the leaf expansion U y^ goes to its own buffer w.zx,
+  // beside the dense rows (the fused downsweep ends with it); the output
+  // permutation adds the dense partial, the same Z + U y^ addition.
+  const bool zx = nvp > 0 && w.zx != nullptr;
   if (fused) STEP(run_tree(h, w, h->tree_down, nvp, prec, s));
   else
     for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  if (zx && !fused) STEP(run_launch(h, w, plan.out, nv, ep, s, nvp, MODE_STORE, prec, false, w.zx));
   STEP(mark(4, s));
   HIP_TRY(hipStreamWaitEvent(s, w.ev_join, 0), "hipStreamWaitEvent(join)");
   STEP(mark(7, s));
-  if (fused) {
+  if (zx) {
     // Y = alpha (Z + U y^)[pinv] + beta Y
     HIP_TRY(launch_permute_out_rm2(w.zn, w.zx, h->d_pinv, alpha, beta, Y, ldy, h->n, nv, nvp, s), "permute out");
   } else if (nvp) {
@@ -991,8 +1012,9 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   // best candidate of one launch; its time (ms, two timed runs) in *tbest
   auto tune_one = [&](Launch& L, int mode_override, float* tbest, bool couple = false) -> int {
     const int pi = L.lowrank ? prec : H2_PREC_FP64;
-    // 0: pipelined, 1-8: balanced (64 vectors only), kWaveRows: a wave per row (rows of <= 64 outputs)
-    const int kcs[12] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8, kWaveRows};
+    // 0: pipelined, 1-8: balanced (64 vectors only), kWaveRows / kWaveTiles: a wave per row / per
+    // 16-vector tile (rows of <= 64 outputs)
+    const int kcs[13] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8, kWaveRows, kWaveTiles};
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
     int best_kc = L.kcp[pi], best_remap = L.remapp[pi];
@@ -1001,11 +1023,12 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
       if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
       if (kc >= 0 && kc <= 8 && nvp != 64) continue;
       if (kc >= 1 && kc <= 8 && L.max_rows > 64) continue;
-      if (kc == kWaveRows && L.max_rows > 64) continue;
+      if ((kc == kWaveRows || kc == kWaveTiles) && L.max_rows > 64) continue;
+      if (kc == kWaveTiles && nvp != 32 && nvp != 64) continue;
       for (int64_t g : grids)
         for (int remap = 0; remap < 2; ++remap) {
           if (g != 0 && g >= L.row_count) continue;
-          if (kc == kWaveRows && remap) continue;  // rows taken grid-stride
+          if ((kc == kWaveRows || kc == kWaveTiles) && remap) continue;  // rows taken grid-stride
           // the dense rows run beside the sweeps: a persistent grid would hold
           // every CU slot and starve them, so they keep one workgroup per row
           if (g != 0 && !L.lowrank) continue;
@@ -1060,7 +1083,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if (rc == H2_OK) rc = tune_list(plan.dense2, &td2);
   if (rc == H2_OK) rc = tune_list(plan.dense_loc, &tl1);
   if (rc == H2_OK) rc = tune_list(plan.dense2_loc, &tl2);
-  if (rc == H2_OK) rc = tune_one(plan.out, MODE_ACCUM, &t_out);
+  if (rc == H2_OK) rc = tune_one(plan.out, w.zx ? MODE_STORE : MODE_ACCUM, &t_out);  // as the product runs it
   if (rc == H2_OK) {
     h->couple_mode[prec] = tcl < tc ? 1 : 0;
     h->dense_mode[prec] = tl1 + tl2 < td1 + td2 ? 1 : 0;
@@ -1086,6 +1109,39 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
       h->sweep_ms[prec][1] = tf / 2;
     }
   }
+  // the dense rows' schedule, timed on whole products (three runs each after
+  // a warm-up) on zeroed input and output buffers
+  if (rc == H2_OK) {
+    double *X = nullptr, *Y = nullptr;
+    const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(h->n, 1) * nvp;
+    if (hipMalloc(reinterpret_cast<void**>(&X), vb) == hipSuccess &&
+        hipMalloc(reinterpret_cast<void**>(&Y), vb) == hipSuccess && hipMemsetAsync(X, 0, vb, s) == hipSuccess) {
+      float best = 1e30f;
+      int best_s = h->sched[prec];
+      for (int sc = 0; sc < 3 && rc == H2_OK; ++sc) {
+        h->sched[prec] = sc;
+        float t = 0.0f;
+        for (int rep = 0; rep < 4 && rc == H2_OK; ++rep) {
+          if (hipEventRecord(e0, s) != hipSuccess) { rc = H2_EHIP; break; }
+          rc = gemv_ws(h, w, false, 1.0, X, h->n, nvp, 0.0, Y, h->n, prec, s);
+          float ms = 0.0f;
+          if (rc == H2_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = H2_EHIP;
+          if (rep > 0) t += ms;
+        }
+        h->sched_ms[prec][sc] = t / 3;
+        if (t < best) {
+          best = t;
+          best_s = sc;
+        }
+      }
+      h->sched[prec] = best_s;
+      if (rc == H2_EHIP) set_error("timing the dense schedules failed");
+    }
+    if (X) (void)hipFree(X);
+    if (Y) (void)hipFree(Y);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;
@@ -1097,8 +1153,8 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
     set_error("unknown precision");
     return H2_EINVAL;
   }
-  if (!(kc >= 0 && kc <= kWaveRows) && kc != 32 && kc != 64) {
-    set_error("kc must be 0-9, 32 or 64");
+  if (!(kc >= 0 && kc <= kWaveTiles) && kc != 32 && kc != 64) {
+    set_error("kc must be 0-10, 32 or 64");
     return H2_EINVAL;
   }
   if (prec == H2_PREC_BF16 && kc != 64) { set_error("the BF16 kernel has kc 64 only"); return H2_EINVAL; }
@@ -1175,6 +1231,11 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
   for (int p = 0; p < 2; ++p) {
     std::snprintf(line, sizeof line, "%s: sweeps %s (per-level %.3fms, fused %.3fms when tuned)\n", pn[p],
                   h->tree_ok && h->sweep_fused[p] ? "fused" : "per level", h->sweep_ms[p][0], h->sweep_ms[p][1]);
+    t += line;
+  }
+  for (int p = 0; p < 3; ++p) {
+    std::snprintf(line, sizeof line, "%s: dense schedule %d (tuned products %.3f / %.3f / %.3f ms)\n", pn[p],
+                  h->sched[p], h->sched_ms[p][0], h->sched_ms[p][1], h->sched_ms[p][2]);
     t += line;
   }
   for (const auto* v : {&h->tree_up, &h->tree_down})

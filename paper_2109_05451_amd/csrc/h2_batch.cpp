@@ -264,10 +264,10 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
 
 int run_blaunch(h2_batch_s* b, const Group& G, const Launch& L, hipStream_t s) {
   const double* data = L.arr == ARR_TRANS ? b->d_trans : b->d_mat;
-  if (L.kc == kWaveRows && L.max_rows <= 64) {
+  if ((L.kc == kWaveRows || L.kc == kWaveTiles) && L.max_rows <= 64) {
     const hipError_t e = launch_wave_rows<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend,
                                                   b->rt.d_in_off, data, G.d_ws, G.d_ws, G.nvp, L.mode,
-                                                  L.max_rows, s, L.grid);
+                                                  L.max_rows, s, L.grid, L.kc == kWaveTiles);
     if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
     return H2_OK;
   }
@@ -467,7 +467,8 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
   hipEvent_t e0, e1;
   HIP_TRYB(hipEventCreate(&e0), "hipEventCreate");
   HIP_TRYB(hipEventCreate(&e1), "hipEventCreate");
-  const int kcs[3] = {32, 64, kWaveRows};  // chunk widths of the LDS-staged kernel; a wave per row
+  // chunk widths of the LDS-staged kernel; a wave per row; a wave per 16-vector tile
+  const int kcs[4] = {32, 64, kWaveRows, kWaveTiles};
   const int64_t grids[4] = {0, 1024, 2048, 4096};
   for (Group& G : b->groups)
     for (auto* v : {&G.up, &G.couple, &G.down, &G.dense, &G.out})
@@ -478,7 +479,8 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
         for (int kc : kcs)
           for (int64_t gsz : grids) {
             if (gsz != 0 && gsz >= L.row_count) continue;
-            if (kc == kWaveRows && L.max_rows > 64) continue;
+            if ((kc == kWaveRows || kc == kWaveTiles) && L.max_rows > 64) continue;
+            if (kc == kWaveTiles && G.nvp != 32 && G.nvp != 64) continue;
             Launch T = L;
             T.kc = kc;
             T.grid = gsz;

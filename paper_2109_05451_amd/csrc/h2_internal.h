@@ -292,8 +292,13 @@ struct h2_op_s {
   std::vector<h2::TreeGroup> tree_up, tree_down;
   int2* d_tree_ranges = nullptr;
   bool tree_ok = false;              // every group fits the fused kernel
-  int sweep_fused[3] = {1, 1, 1};    // per precision (FP64, FP32; BF16 has none): use the fused sweeps
+  int sweep_fused[3] = {0, 0, 0};    // per precision (FP64, FP32; BF16 has none): use the fused sweeps
   float sweep_ms[3][2] = {};         // tuned times of the sweeps: per level, fused
+  // multi-vector path, per precision: where the dense rows run (h2_tune):
+  // 0 halves beside the upsweep and the downsweep, 1 the first half beside the
+  // coupling launch instead, 2 both halves from the start
+  int sched[3] = {0, 0, 0};
+  float sched_ms[3][3] = {};
   int64_t index_bytes = 0;
   // the serialized header and index sections (bytes before U), 8-byte aligned,
   // and the representation's total size: the host view of the structure
@@ -355,12 +360,13 @@ hipError_t launch_permute_in_rm(const double* X, int64_t ldx, const int32_t* pin
 hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double alpha, double beta, double* Y,
                                  int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s);
 // The multi-vector row product with one wave per row (kc code kWaveRows of
-// the tuner); grid = workgroups (0: enough for every row at once)
-constexpr int kWaveRows = 9;
+// the tuner), or one wave per 16-vector tile of a row (kWaveTiles); grid =
+// workgroups (0: enough for every row at once)
+constexpr int kWaveRows = 9, kWaveTiles = 10;
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid);
+                            hipStream_t s, int64_t grid, bool narrow = false);
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
                        const int32_t* colend, const int64_t* in_off, const T* data, double* const bufs[4], int nvp,

@@ -257,11 +257,21 @@ hipError_t launch_permute_out_rm2(const double* Z, const double* Z2, const int32
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid) {
+                            hipStream_t s, int64_t grid, bool narrow) {
   if (nrows == 0) return hipSuccess;
   if (max_rows > 64) return hipErrorInvalidValue;
+  // narrow: a wave per 16-vector tile (NT waves per row, more waves resident); else a wave per row, or
+  // two when one wave's accumulators would leave a single wave per SIMD
 #define H2_WR(NT, MT)                                                                                    \
   do {                                                                                                   \
+    if (narrow && (NT == 2 || NT == 4)) {                                                                \
+      constexpr int RPWN = 4 / NT;                                                                       \
+      const int64_t needn = (nrows + RPWN - 1) / RPWN;                                                   \
+      const dim3 gn((unsigned)(grid > 0 && grid < needn ? grid : needn)), bn(kT);                        \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, 1, MT>), gn, bn, 0, s, rows, nrows, colend, in_off, data, in, out, \
+                         mode);                                                                          \
+      break;                                                                                             \
+    }                                                                                                    \
     constexpr int NTW = (MT * NT > 8 && NT % 2 == 0) ? NT / 2 : NT, RPW = 4 / (NT / NTW);               \
     const int64_t need = (nrows + RPW - 1) / RPW;                                                        \
     const dim3 g((unsigned)(grid > 0 && grid < need ? grid : need)), b(kT);                              \
@@ -287,9 +297,9 @@ hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* c
   return hipGetLastError();
 }
 template hipError_t launch_wave_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
-                                             const double*, double*, int, int, int, hipStream_t, int64_t);
+                                             const double*, double*, int, int, int, hipStream_t, int64_t, bool);
 template hipError_t launch_wave_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
-                                            const double*, double*, int, int, int, hipStream_t, int64_t);
+                                            const double*, double*, int, int, int, hipStream_t, int64_t, bool);
 
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,

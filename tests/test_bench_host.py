@@ -53,7 +53,8 @@ def test_traffic_only_from_a_summary_of_the_same_kernel_source(tmp_path, monkeyp
     src = tmp_path / "paper_2109_05451_amd" / "csrc"
     src.mkdir(parents=True)
     (src / "h2_kernels.hip").write_bytes(b"// kernels\n")
-    md5 = hashlib.md5(b"// kernels\n").hexdigest()
+    (src / "h2_tree_kernels.hip").write_bytes(b"// more kernels\n")
+    md5 = hashlib.md5(b"// kernels\n// more kernels\n").hexdigest()
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "k_rows_cfg_nv1.md").write_text(f"kernel_source_md5: `{md5}`\n\n"
@@ -62,5 +63,6 @@ def test_traffic_only_from_a_summary_of_the_same_kernel_source(tmp_path, monkeyp
     assert bench.measured_traffic("cfg", 1, "coupling") == 1.5e9
     assert bench.measured_traffic("cfg", 1, "dense") is None       # no figure for that launch
     assert bench.measured_traffic("cfg", 64, "coupling") is None   # no summary for that workload
-    (src / "h2_kernels.hip").write_bytes(b"// kernels, changed\n")
+    assert bench.measured_traffic("cfg", 1, "coupling", "bf16") is None  # no summary for that precision
+    (src / "h2_tree_kernels.hip").write_bytes(b"// more kernels, changed\n")
     assert bench.measured_traffic("cfg", 1, "coupling") is None    # taken on another kernel source
