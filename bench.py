@@ -237,6 +237,41 @@ def latency_gpu(g, X, Y, nv, calls, torch):
     return np.array([s.elapsed_time(e) for s, e in ev])
 
 
+def small_operator_latency(torch, calls: int = 200) -> dict:
+    """Latency of one product on the 4096-point 2D operator (leaf 64, 4x4
+    Chebyshev, nv = 1; about 22 MB, so it lives in the on-die cache): HIP
+    events around each call on a stream of its own, launched one by one and
+    replayed from a captured HIP graph (h2_graph), p50 / p99 over `calls`."""
+    import h2gen
+    from paper_2109_05451_amd import H2Operator
+    buf = h2gen.build_config("c1_2d_4096")
+    g = H2Operator(buf.array)
+    n = g.n
+    X = torch.from_numpy(np.asfortranarray(h2gen.vectors(n, 1, 2001))).cuda()
+    Y = torch.empty((1, n), dtype=torch.float64, device="cuda").t()
+    stream = torch.cuda.Stream()
+    out = {"workload": "c1_2d_4096: " + WORKLOADS["c1_2d_4096"] + ", nv=1",
+           "launches_per_product": launches_per_product(g)}
+    for mode in ("launches", "graph"):
+        g.graph(mode == "graph")
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                g.gemv_raw("N", 1.0, X.data_ptr(), n, 1, 0.0, Y.data_ptr(), n, stream.cuda_stream)
+            for a, b in ev:
+                a.record(stream)
+                g.gemv_raw("N", 1.0, X.data_ptr(), n, 1, 0.0, Y.data_ptr(), n, stream.cuda_stream)
+                b.record(stream)
+        torch.cuda.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in ev])
+        out[mode] = {"p50_us": round(1e3 * float(np.percentile(t, 50)), 1),
+                     "p99_us": round(1e3 * float(np.percentile(t, 99)), 1)}
+    g.graph(False)
+    g.close()
+    return out
+
+
 def cpu_baseline(buf, X, budget_s=30.0):
     """The oracle as it stands, timed on the host on a bounded sample: whole
     products at nv = 1 while the budget lasts (at least one)."""
@@ -602,6 +637,7 @@ def main():
         c3 = h2gen.CONFIGS["c3_3d_512k"]
         work.append(run_workload("c3_3d_512k", [(64, "fp64")] + [(64, p) for p in c3["precisions"]], args, torch))
 
+    small = small_operator_latency(torch) if args.config == "c2_2d_1m" and not args.no_variants else None
     name, buf, st, rows, results = work[0]
     r = results[(nv, "fp64")]
     alg = r["alg"]
@@ -650,6 +686,7 @@ def main():
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4),
                        "samples": int(r.get("lat_samples", len(r["per_call"]))),
                        "launches_per_product": r.get("launches")},
+        "small_operator_latency": small,
         "hbm_copy_measured_gbs": round(copy_gbs, 1),
         "measured_peaks": dict(peaks or {}, datasheet={"hbm_gbs": HBM_PEAK_GBS, "fp64_tflops": FP64_PEAK_TFLOPS,
                                                         "bf16_tflops": BF16_PEAK_TFLOPS}),

@@ -181,6 +181,19 @@ int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx,
 int h2_gemv_noalloc(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv,
                     double beta, double* Y, int64_t ldy, void* stream);
 
+/* Graph replay of h2_gemv / h2_gemv_ex (enable != 0): the first call with a
+ * given set of arguments (op, precision, X, ldx, nv, alpha, beta, Y, ldy and
+ * a non-null stream) captures its launch sequence into a HIP graph, and
+ * later calls with the same arguments replay it with one launch (X is read
+ * afresh at every replay).  Up to 8 graphs are kept per handle, the least
+ * recently used dropped first; retuning (h2_tune, h2_tune_set,
+ * h2_set_sweeps, h2_set_dense_grid) drops them all.  For repeated products on
+ * the same buffers, where launching the sequence costs more than the GPU
+ * work (small operators).  Calls on the null stream, or while profiling, are
+ * not captured.  No memset nodes are captured.  Disabling drops the graphs.
+ * Synchronizes the device.  Errors: H2_EINVAL, H2_EHIP. */
+int h2_graph(h2_handle h, int enable);
+
 /* Build the device copy of the low-rank data in precision `prec` now
  * (no-op for H2_PREC_FP64 or when it exists).  Synchronous. */
 int h2_prepare(h2_handle h, int prec);

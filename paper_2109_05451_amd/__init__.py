@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libh2gemv.so")
 H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
 # exported symbols of include/h2.h, in declaration order
-EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_gemv_noalloc", "h2_prepare", "h2_reserve", "h2_tune",
+EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_gemv_noalloc", "h2_graph", "h2_prepare", "h2_reserve", "h2_tune",
            "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set", "h2_set_dense_grid", "h2_set_sweeps",
            "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_load_ex", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     lib.h2_gemv_ex.restype = ci
     lib.h2_gemv_noalloc.argtypes = [vp, ctypes.c_char, dbl, vp, i64, i64, dbl, vp, i64, vp]
     lib.h2_gemv_noalloc.restype = ci
+    lib.h2_graph.argtypes = [vp, ci]
+    lib.h2_graph.restype = ci
     lib.h2_prepare.argtypes = [vp, ci]
     lib.h2_prepare.restype = ci
     lib.h2_reserve.argtypes = [vp, i64]
@@ -291,6 +293,10 @@ class H2Operator:
         p = H2Profile()
         _check(load_library().h2_profile_read(self._h, ctypes.byref(p)))
         return p.as_dict()
+
+    def graph(self, enable: bool = True):
+        """Replay repeated products on the same buffers from captured HIP graphs (see h2_graph)."""
+        _check(load_library().h2_graph(self._h, 1 if enable else 0))
 
     def prepare(self, precision: str):
         _check(load_library().h2_prepare(self._h, PRECISIONS[precision]))

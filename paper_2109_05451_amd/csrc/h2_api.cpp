@@ -134,7 +134,16 @@ void add_gather_phase(h2_op_s* h, const std::vector<RowSpec>& rows, int in, int 
   if (L.row_count) dst.push_back(L);
 }
 
+// Destroy the captured graphs of h2_gemv (their launch parameters are stale
+// after retuning); the device must be idle or the graphs finished.
+void drop_graphs(h2_op_s* h) {
+  for (GraphEntry& g : h->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
 void free_device(h2_op_s* h) {
+  drop_graphs(h);
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   F(h->d_mat); F(h->d_trans); F(h->d_perm); F(h->d_pinv); F(h->d_mat32); F(h->d_trans32);
   F(h->d_mat16); F(h->d_trans16);
@@ -957,8 +966,56 @@ int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx,
     return H2_OK;
   }
   if ((rc = ensure_workspace(h, prec == H2_PREC_BF16 ? kPassVectorsMfma : nv)) != H2_OK) return rc;
+  if (h->use_graph && s != nullptr && !h->profiling) {
+    // replay the call's captured launch sequence, or capture it now (the
+    // reduced-precision copy is made first: its allocation and
+    // synchronization cannot be captured)
+    if (prec == H2_PREC_FP32 && (rc = prepare_f32(h)) != H2_OK) return rc;
+    if (prec == H2_PREC_BF16 && (rc = prepare_bf16(h)) != H2_OK) return rc;
+    const GraphKey key{trans, prec, X, ldx, nv, alpha, beta, Y, ldy, s};
+    for (GraphEntry& g : h->graphs)
+      if (g.key == key) {
+        g.last_use = ++h->graph_clock;
+        HIP_TRY(hipGraphLaunch(g.exec, s), "hipGraphLaunch");
+        return H2_OK;
+      }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    rc = gemv_ws(h, h->ws, trans, alpha, X, ldx, nv, beta, Y, ldy, prec, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rc != H2_OK || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != H2_OK) return rc;
+      return hip_fail(ec, "hipStreamEndCapture");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+    if (h->graphs.size() >= kMaxGraphs) {  // drop the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < h->graphs.size(); ++i)
+        if (h->graphs[i].last_use < h->graphs[lru].last_use) lru = i;
+      HIP_TRY(hipStreamSynchronize(h->graphs[lru].key.s), "hipStreamSynchronize(graph)");
+      (void)hipGraphExecDestroy(h->graphs[lru].exec);
+      h->graphs.erase(h->graphs.begin() + (long)lru);
+    }
+    h->graphs.push_back(GraphEntry{key, exec, ++h->graph_clock});
+    HIP_TRY(hipGraphLaunch(exec, s), "hipGraphLaunch");
+    return H2_OK;
+  }
   if ((rc = gemv_ws(h, h->ws, trans, alpha, X, ldx, nv, beta, Y, ldy, prec, s)) != H2_OK) return rc;
   if (h->profiling) ++h->prof.calls;
+  return H2_OK;
+}
+
+int h2_graph(h2_handle h, int enable) {
+  if (!h) { set_error("null handle"); return H2_EINVAL; }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
+  h->use_graph = enable != 0;
   return H2_OK;
 }
 
@@ -985,6 +1042,8 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if (nv <= kPassVectors && prec != H2_PREC_BF16) return H2_OK;  // streaming path: nothing to tune
   DeviceGuard guard(h->device);
   if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);  // captured with the old launch parameters
   int rc;
   if ((rc = h2_prepare(h, prec)) != H2_OK) return rc;
   if ((rc = ensure_workspace(h, prec == H2_PREC_BF16 ? kPassVectorsMfma : nv)) != H2_OK) return rc;
@@ -1161,6 +1220,7 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
   if (grid < 0) { set_error("grid < 0"); return H2_EINVAL; }
   DeviceGuard guard(h->device);
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
   Plan& P = h->planN;
   for (auto* v : {&P.up, &P.couple, &P.down, &P.couple_loc})
     for (Launch& L : *v) {
@@ -1187,6 +1247,7 @@ int h2_set_dense_grid(h2_handle h, int64_t workgroups) {
   if (!h || workgroups < -1) { set_error("bad handle or workgroups"); return H2_EINVAL; }
   DeviceGuard guard(h->device);
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
   h->dense_grid_mv = workgroups;
   return H2_OK;
 }
@@ -1200,6 +1261,7 @@ int h2_set_sweeps(h2_handle h, int prec, int fused) {
   }
   DeviceGuard guard(h->device);
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
   h->sweep_fused[prec] = fused ? 1 : 0;
   return H2_OK;
 }

@@ -148,6 +148,29 @@ struct TreeGroup {
   bool trans_data = false;  // rows read the transposed basis copies (upsweep)
 };
 
+// A captured h2_gemv call (HIP graph replay): every argument that the
+// launch sequence bakes in.
+struct GraphKey {
+  bool trans;
+  int prec;
+  const double* X;
+  int64_t ldx, nv;
+  double alpha, beta;
+  double* Y;
+  int64_t ldy;
+  hipStream_t s;
+  bool operator==(const GraphKey& o) const {
+    return trans == o.trans && prec == o.prec && X == o.X && ldx == o.ldx && nv == o.nv && alpha == o.alpha &&
+           beta == o.beta && Y == o.Y && ldy == o.ldy && s == o.s;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+constexpr size_t kMaxGraphs = 8;
+
 struct Epilogue {
   const double* zn;     // dense partial, n x nv (ld n)
   const int32_t* perm;  // tree position -> original index
@@ -306,6 +329,10 @@ struct h2_op_s {
   std::vector<uint64_t> prefix;
   int64_t prefix_len = 0, file_len = 0;
   h2::Workspace ws;  // the handle's own workspace (h2_gemv), allocated on first use
+  // captured calls of h2_gemv / h2_gemv_ex (h2_graph), least recently used dropped first
+  bool use_graph = false;
+  std::vector<h2::GraphEntry> graphs;
+  uint64_t graph_clock = 0;
   // side stream and fork/join events of h2_gemv_noalloc, created at load
   // (its buffers are views of the fixed scratch array)
   h2::Workspace na;
