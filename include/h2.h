@@ -39,7 +39,8 @@ enum {
                           leading dimension < n, X and Y overlap */
   H2_EIO = -2,         /* file could not be read */
   H2_EFORMAT = -3,     /* not a valid representation (magic, version, sizes,
-                          tree, permutation, CSR structure) */
+                          tree, permutation, CSR structure, a point
+                          dimension above 64) */
   H2_ENOMEM = -4,      /* host or device allocation failed */
   H2_EHIP = -5,        /* other HIP runtime error (message has the HIP text) */
   H2_EUNSUPPORTED = -6 /* valid, but outside this build's limits (a rank or a

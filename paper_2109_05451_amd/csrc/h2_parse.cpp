@@ -56,7 +56,7 @@ int parse(const uint8_t* buf, int64_t len, Parsed* p) {
   const int64_t n = hd[0], q = hd[1], nnodes = hd[2], dim = hd[3];
   const int64_t ndense = tail[0], total = tail[1];
   if (total != len) return fail(H2_EFORMAT, "size in header differs from buffer size");
-  if (n < 1 || q < 0 || q > 40 || nnodes < 1 || dim < 0 || ndense < 0)
+  if (n < 1 || q < 0 || q > 40 || nnodes < 1 || dim < 0 || dim > 64 || ndense < 0)
     return fail(H2_EFORMAT, "bad header counts");
   if (!(flags & 2u) && dim != 0) return fail(H2_EFORMAT, "dimension set without points");
   if (n >= (int64_t(1) << 31) || nnodes >= (int64_t(1) << 31) || ndense >= (int64_t(1) << 31))
@@ -139,8 +139,10 @@ int parse(const uint8_t* buf, int64_t len, Parsed* p) {
       const int64_t* rp = P.s_rowptr + rb;
       P.rp_base[l] = rb; P.blk_base[l] = bb; P.sdat[l] = sd;
       if (rp[0] != 0 || rp[nl] != P.nadm[l]) return fail(H2_EFORMAT, "coupling row pointer ends");
-      for (int64_t t = 0; t < nl; ++t) {
+      // the whole pointer array first, so that no row's range runs past the level's columns
+      for (int64_t t = 0; t < nl; ++t)
         if (rp[t + 1] < rp[t]) return fail(H2_EFORMAT, "coupling row pointer decreases");
+      for (int64_t t = 0; t < nl; ++t) {
         for (int64_t b = rp[t]; b < rp[t + 1]; ++b) {
           const int64_t s = P.s_col[bb + b];
           if (s < 0 || s >= nl) return fail(H2_EFORMAT, "coupling column out of range");
@@ -159,8 +161,9 @@ int parse(const uint8_t* buf, int64_t len, Parsed* p) {
   {
     const int64_t* rp = P.d_rowptr;
     if (rp[0] != 0 || rp[P.nleaves] != ndense) return fail(H2_EFORMAT, "dense row pointer ends");
-    for (int64_t t = 0; t < P.nleaves; ++t) {
+    for (int64_t t = 0; t < P.nleaves; ++t)
       if (rp[t + 1] < rp[t]) return fail(H2_EFORMAT, "dense row pointer decreases");
+    for (int64_t t = 0; t < P.nleaves; ++t) {
       const int64_t mt = P.hi[P.leaf0 + t] - P.lo[P.leaf0 + t];
       for (int64_t b = rp[t]; b < rp[t + 1]; ++b) {
         const int64_t s = P.d_col[b];
