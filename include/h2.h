@@ -212,10 +212,9 @@ int h2_reserve(h2_handle h, int64_t nv_max);
  * workspace buffers, and the fastest is kept for later calls in that
  * precision (the dense rows, always FP64, keep theirs in the FP64 entry);
  * then the fused sweeps are timed against the tuned per-level sweeps and the
- * faster form is kept (h2_set_sweeps), and three schedules of the dense rows
- * on their second stream (halves beside the upsweep and the downsweep; the
- * first half beside the coupling launch instead; both from the start) are
- * timed on whole products (zeroed input) and the fastest is kept.
+ * faster form is kept (h2_set_sweeps), and the four schedules of
+ * h2_set_schedule are timed on whole products (zeroed input) and the
+ * fastest is kept.
  * Results do not depend on the choice: every candidate sums each output in
  * the same order, so they are bitwise identical.  No-op for nv <= 4 outside
  * BF16 (the streaming kernel has nothing to tune).  Synchronous; must not run concurrently with other calls on the
@@ -292,6 +291,22 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
  * sooner.  Results do not change.  Synchronizes the device.
  * Errors: H2_EINVAL. */
 int h2_set_dense_grid(h2_handle h, int64_t workgroups);
+
+/* Where the multi-vector path (op 'N', more than 4 vectors, or BF16) runs
+ * its dense near-field rows and its coupling rows, for precision `prec`:
+ *   0  the dense rows' first half on a second stream beside the upsweep, the
+ *      second half beside the downsweep and the leaf expansion
+ *   1  the first half beside the coupling launch instead
+ *   2  both halves from the start
+ *   3  both halves from the start, and the coupling rows of the leaf level
+ *      (they need only the leaf products of the upsweep) on a third stream
+ *      beside the upper upsweep, the other levels' coupling rows and the
+ *      upper downsweep; the last downsweep level waits for them (not with
+ *      the fused sweeps, nor for FP32 passes of 64 vectors, which take
+ *      schedule 2 instead)
+ * Results are bitwise the same; h2_tune keeps the fastest.  Synchronizes the
+ * device.  Errors: H2_EINVAL. */
+int h2_set_schedule(h2_handle h, int prec, int schedule);
 
 /* How the multi-vector path (op 'N', 64-vector passes or fewer, FP64 and
  * FP32) runs the upsweep, the downsweep and the leaf expansion: fused != 0

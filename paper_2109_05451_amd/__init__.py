@@ -20,8 +20,8 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_gemv_noalloc", "h2_graph", "h2_prepare", "h2_reserve", "h2_tune",
-           "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set", "h2_set_dense_grid", "h2_set_sweeps",
-           "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_load_ex", "h2_batch_gemv",
+           "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set", "h2_set_dense_grid", "h2_set_schedule",
+           "h2_set_sweeps", "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_load_ex", "h2_batch_gemv",
            "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
 
@@ -132,6 +132,8 @@ def load_library(path: str = LIB_PATH):
     lib.h2_set_dense_grid.restype = ci
     lib.h2_set_sweeps.argtypes = [vp, ci, ci]
     lib.h2_set_sweeps.restype = ci
+    lib.h2_set_schedule.argtypes = [vp, ci, ci]
+    lib.h2_set_schedule.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
     lib.h2_stats.restype = ci
     lib.h2_level_stats.argtypes = [vp, i64, ctypes.POINTER(H2LevelStats)]
@@ -247,6 +249,10 @@ class H2Operator:
     def set_dense_grid(self, workgroups: int = -1):
         """Workgroups of the multi-vector dense launches (see h2_set_dense_grid)."""
         _check(load_library().h2_set_dense_grid(self._h, int(workgroups)))
+
+    def set_schedule(self, precision: str = "fp64", schedule: int = 0):
+        """Where the multi-vector dense and coupling rows run, 0-3 (see h2_set_schedule)."""
+        _check(load_library().h2_set_schedule(self._h, PRECISIONS[precision], int(schedule)))
 
     def set_sweeps(self, precision: str = "fp64", fused: bool = True):
         """Fused subtree sweeps or one launch per level (see h2_set_sweeps)."""

@@ -302,6 +302,14 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
     for (int64_t hh = 1; hh <= q; ++hh) add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
     add_stream_phase(h, R.couple, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple);
     {
+      // the leaf level's coupling rows are the last ones emitted
+      const size_t nq = (size_t)(lp[q + 1] - lp[q]);
+      const std::vector<RowSpec> rest(R.couple.begin(), R.couple.end() - (long)nq),
+          deep(R.couple.end() - (long)nq, R.couple.end());
+      add_stream_phase(h, deep, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple_deep);
+      add_stream_phase(h, rest, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple_rest);
+    }
+    {
       // the same rows in tree order; the dense rows in two halves of the domain
       const std::vector<size_t> oc = order_by_position(R.couple);
       add_stream_rows(h, R.couple, oc.data(), oc.size(), ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, plan.couple_loc);
@@ -474,7 +482,8 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
     pinv[P.perm[i]] = (int32_t)i;
   }
   for (const auto* v : {&h->planN.up, &h->planN.couple, &h->planN.down, &h->planN.dense, &h->planN.dense2,
-                        &h->planN.couple_loc, &h->planN.dense_loc, &h->planN.dense2_loc})
+                        &h->planN.couple_loc, &h->planN.dense_loc, &h->planN.dense2_loc, &h->planN.couple_deep,
+                        &h->planN.couple_rest})
     for (const Launch& L : *v)
       if (L.kind != KIND_STREAM) h->mfma_ok = false;
   int64_t ib = 0;
@@ -598,10 +607,11 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   const int kcw = L.kcp[lowp ? H2_PREC_FP32 : H2_PREC_FP64];
   if (nvp > 0 && (kcw == kWaveRows || kcw == kWaveTiles) && L.max_rows <= 64) {
     const bool narrow = kcw == kWaveTiles;
+    const int rm = L.remapp[lowp ? H2_PREC_FP32 : H2_PREC_FP64];
     e = lowp ? launch_wave_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow)
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm)
              : launch_wave_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow);
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm);
   } else if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
@@ -712,10 +722,10 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   const std::vector<Launch>& couple = cm == 1 ? plan.couple_loc : plan.couple;
   const std::vector<Launch>& dense1 = dm == 1 ? plan.dense_loc : plan.dense;
   const std::vector<Launch>& dense2 = dm == 1 ? plan.dense2_loc : plan.dense2;
-  std::array<hipEvent_t, 11>* ev = nullptr;
+  std::array<hipEvent_t, 13>* ev = nullptr;
   if (h->profiling && &w == &h->ws) {
     if (h->ev_used == h->ev_pool.size()) {
-      std::array<hipEvent_t, 11> set{};
+      std::array<hipEvent_t, 13> set{};
       for (auto& e : set) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
       h->ev_pool.push_back(set);
     }
@@ -735,8 +745,16 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   // dense near field on the side stream, concurrent with the low-rank phases.
   // Schedule (multi-vector path, per precision, h2_tune): 0 the first half
   // beside the upsweep, the second beside the downsweep; 1 the first half
-  // beside the coupling launch instead; 2 both halves from the start.
+  // beside the coupling launch instead; 2 both halves from the start; 3 as 2,
+  // and the leaf level's coupling rows on a third stream as soon as the leaf
+  // products are done, beside the upper upsweep, the other levels' coupling
+  // rows and the upper downsweep (the last downsweep level waits for them).
   const int sched = nvp > 0 && !trans ? h->sched[pidx] : 0;
+  const bool fused = use_tree(h, w, trans, nvp, prec);
+  // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
+  const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
+  const bool split = sched == 3 && !fused && !x32 && !plan.down.empty() && !plan.couple_deep.empty() &&
+                     !plan.up.empty();
   auto fork_dense1 = [&]() -> int {
     HIP_TRY(hipEventRecord(w.ev_fork, s), "hipEventRecord(fork)");
     HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");
@@ -746,19 +764,32 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
     return H2_OK;
   };
   if (sched != 1) STEP(fork_dense1());
-  const bool fused = use_tree(h, w, trans, nvp, prec);
-  if (fused) STEP(run_tree(h, w, h->tree_up, nvp, prec, s));
-  else
-    for (const Launch& L : plan.up) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
-  // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
-  const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
+  if (fused) {
+    STEP(run_tree(h, w, h->tree_up, nvp, prec, s));
+  } else {
+    for (size_t i = 0; i < plan.up.size(); ++i) {
+      STEP(run_launch(h, w, plan.up[i], nv, ep, s, nvp, -1, prec));
+      if (split && i == 0) {  // the leaf level's x^ is complete
+        HIP_TRY(hipEventRecord(w.ev_deep, s), "hipEventRecord(deep)");
+        HIP_TRY(hipStreamWaitEvent(w.side2, w.ev_deep, 0), "hipStreamWaitEvent(deep)");
+        STEP(mark(11, w.side2));
+        for (const Launch& L : plan.couple_deep) STEP(run_launch(h, w, L, nv, ep, w.side2, nvp, -1, prec));
+        STEP(mark(12, w.side2));
+        HIP_TRY(hipEventRecord(w.ev_deep_done, w.side2), "hipEventRecord(deep done)");
+      }
+    }
+  }
   if (x32) HIP_TRY(launch_to_f32(w.xh, w.xh32, h->H * (int64_t)nvp, s), "x^ to FP32");
   if (sched == 1) STEP(fork_dense1());
   STEP(mark(2, s));
-  for (const Launch& L : couple) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec, x32));
+  for (const Launch& L : (split ? plan.couple_rest : couple)) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec, x32));
   STEP(mark(3, s));
+  if (!split) {  // no third-stream interval: a zero one
+    STEP(mark(11, s));
+    STEP(mark(12, s));
+  }
   // second half of the dense rows, beside the downsweep and the leaf expansion
-  if (sched != 2) {
+  if (sched != 2 && sched != 3) {
     HIP_TRY(hipEventRecord(w.ev_mid, s), "hipEventRecord(mid)");
     HIP_TRY(hipStreamWaitEvent(w.side, w.ev_mid, 0), "hipStreamWaitEvent(mid)");
   }
@@ -770,9 +801,15 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   // beside the dense rows (the fused downsweep ends with it); the output
   // permutation adds the dense partial, the same Z + U y^ addition.
   const bool zx = nvp > 0 && w.zx != nullptr;
-  if (fused) STEP(run_tree(h, w, h->tree_down, nvp, prec, s));
-  else
-    for (const Launch& L : plan.down) STEP(run_launch(h, w, L, nv, ep, s, nvp, -1, prec));
+  if (fused) {
+    STEP(run_tree(h, w, h->tree_down, nvp, prec, s));
+  } else {
+    for (size_t i = 0; i < plan.down.size(); ++i) {
+      if (split && i + 1 == plan.down.size())  // the leaf level's y^ needs its coupling rows
+        HIP_TRY(hipStreamWaitEvent(s, w.ev_deep_done, 0), "hipStreamWaitEvent(deep done)");
+      STEP(run_launch(h, w, plan.down[i], nv, ep, s, nvp, -1, prec));
+    }
+  }
   if (zx && !fused) STEP(run_launch(h, w, plan.out, nv, ep, s, nvp, MODE_STORE, prec, false, w.zx));
   STEP(mark(4, s));
   HIP_TRY(hipStreamWaitEvent(s, w.ev_join, 0), "hipStreamWaitEvent(join)");
@@ -882,7 +919,10 @@ int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap) {
       (e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&w->ev_mid, hipEventDisableTiming)) != hipSuccess) {
+      (e = hipEventCreateWithFlags(&w->ev_mid, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&w->side2, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&w->ev_deep, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&w->ev_deep_done, hipEventDisableTiming)) != hipSuccess) {
     ws_destroy(w);
     return hip_fail(e, "workspace allocation");
   }
@@ -899,6 +939,9 @@ void ws_destroy(Workspace* w) {
   if (w->ev_join) (void)hipEventDestroy(w->ev_join);
   if (w->ev_mid) (void)hipEventDestroy(w->ev_mid);
   if (w->side) (void)hipStreamDestroy(w->side);
+  if (w->ev_deep) (void)hipEventDestroy(w->ev_deep);
+  if (w->ev_deep_done) (void)hipEventDestroy(w->ev_deep_done);
+  if (w->side2) (void)hipStreamDestroy(w->side2);
   *w = Workspace();
 }
 
@@ -1087,7 +1130,6 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
       for (int64_t g : grids)
         for (int remap = 0; remap < 2; ++remap) {
           if (g != 0 && g >= L.row_count) continue;
-          if ((kc == kWaveRows || kc == kWaveTiles) && remap) continue;  // rows taken grid-stride
           // the dense rows run beside the sweeps: a persistent grid would hold
           // every CU slot and starve them, so they keep one workgroup per row
           if (g != 0 && !L.lowrank) continue;
@@ -1138,6 +1180,11 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if (rc == H2_OK) rc = tune_list(plan.down, &t_down);
   if (rc == H2_OK) rc = tune_list(plan.couple, &tc, true);
   if (rc == H2_OK) rc = tune_list(plan.couple_loc, &tcl, true);
+  float tcd = 0, tcr = 0;
+  if (rc == H2_OK) rc = tune_list(plan.couple_deep, &tcd, true);
+  if (rc == H2_OK) rc = tune_list(plan.couple_rest, &tcr, true);
+  (void)tcd;
+  (void)tcr;
   if (rc == H2_OK) rc = tune_list(plan.dense, &td1);
   if (rc == H2_OK) rc = tune_list(plan.dense2, &td2);
   if (rc == H2_OK) rc = tune_list(plan.dense_loc, &tl1);
@@ -1177,7 +1224,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
         hipMalloc(reinterpret_cast<void**>(&Y), vb) == hipSuccess && hipMemsetAsync(X, 0, vb, s) == hipSuccess) {
       float best = 1e30f;
       int best_s = h->sched[prec];
-      for (int sc = 0; sc < 3 && rc == H2_OK; ++sc) {
+      for (int sc = 0; sc < 4 && rc == H2_OK; ++sc) {
         h->sched[prec] = sc;
         float t = 0.0f;
         for (int rep = 0; rep < 4 && rc == H2_OK; ++rep) {
@@ -1222,7 +1269,7 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
   drop_graphs(h);
   Plan& P = h->planN;
-  for (auto* v : {&P.up, &P.couple, &P.down, &P.couple_loc})
+  for (auto* v : {&P.up, &P.couple, &P.down, &P.couple_loc, &P.couple_deep, &P.couple_rest})
     for (Launch& L : *v) {
       L.kcp[prec] = kc;
       L.gridp[prec] = grid;
@@ -1249,6 +1296,21 @@ int h2_set_dense_grid(h2_handle h, int64_t workgroups) {
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
   drop_graphs(h);
   h->dense_grid_mv = workgroups;
+  return H2_OK;
+}
+
+int h2_set_schedule(h2_handle h, int prec, int schedule) {
+  if (!h) { set_error("null handle"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32 && prec != H2_PREC_BF16) {
+    set_error("unknown precision");
+    return H2_EINVAL;
+  }
+  if (schedule < 0 || schedule > 3) { set_error("schedule must be 0-3"); return H2_EINVAL; }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
+  h->sched[prec] = schedule;
   return H2_OK;
 }
 
@@ -1296,8 +1358,8 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
     t += line;
   }
   for (int p = 0; p < 3; ++p) {
-    std::snprintf(line, sizeof line, "%s: dense schedule %d (tuned products %.3f / %.3f / %.3f ms)\n", pn[p],
-                  h->sched[p], h->sched_ms[p][0], h->sched_ms[p][1], h->sched_ms[p][2]);
+    std::snprintf(line, sizeof line, "%s: dense schedule %d (tuned products %.3f / %.3f / %.3f / %.3f ms)\n",
+                  pn[p], h->sched[p], h->sched_ms[p][0], h->sched_ms[p][1], h->sched_ms[p][2], h->sched_ms[p][3]);
     t += line;
   }
   for (const auto* v : {&h->tree_up, &h->tree_down})
@@ -1309,6 +1371,8 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
   const Plan& P = h->planN;
   dump("up", P.up);
   dump("couple", P.couple);
+  dump("couple_deep", P.couple_deep);
+  dump("couple_rest", P.couple_rest);
   dump("couple_tree", P.couple_loc);
   dump("down", P.down);
   dump("dense1", P.dense);
@@ -1357,12 +1421,12 @@ int h2_profile_read(h2_handle h, h2_profile_t* out) {
     auto& e = h->ev_pool[i];
     HIP_TRY(hipEventSynchronize(e[8]), "hipEventSynchronize");
     HIP_TRY(hipEventSynchronize(e[6]), "hipEventSynchronize");
-    float t[8];
-    const int from[8] = {0, 1, 2, 3, 5, 7, 0, 10}, to[8] = {1, 2, 3, 4, 9, 8, 8, 6};
-    for (int k = 0; k < 8; ++k) HIP_TRY(hipEventElapsedTime(&t[k], e[from[k]], e[to[k]]), "hipEventElapsedTime");
+    float t[9];
+    const int from[9] = {0, 1, 2, 3, 5, 7, 0, 10, 11}, to[9] = {1, 2, 3, 4, 9, 8, 8, 6, 12};
+    for (int k = 0; k < 9; ++k) HIP_TRY(hipEventElapsedTime(&t[k], e[from[k]], e[to[k]]), "hipEventElapsedTime");
     h->prof.ms_permute += t[0];
     h->prof.ms_upsweep += t[1];
-    h->prof.ms_coupling += t[2];
+    h->prof.ms_coupling += t[2] + t[8];
     h->prof.ms_downsweep += t[3];
     h->prof.ms_dense += t[4] + t[7];
     h->prof.ms_leaf_out += t[5];

@@ -267,7 +267,7 @@ int run_blaunch(h2_batch_s* b, const Group& G, const Launch& L, hipStream_t s) {
   if ((L.kc == kWaveRows || L.kc == kWaveTiles) && L.max_rows <= 64) {
     const hipError_t e = launch_wave_rows<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend,
                                                   b->rt.d_in_off, data, G.d_ws, G.d_ws, G.nvp, L.mode,
-                                                  L.max_rows, s, L.grid, L.kc == kWaveTiles);
+                                                  L.max_rows, s, L.grid, L.kc == kWaveTiles, L.remapp[0]);
     if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
     return H2_OK;
   }
@@ -474,16 +474,19 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
     for (auto* v : {&G.up, &G.couple, &G.down, &G.dense, &G.out})
       for (Launch& L : *v) {
         float best = 1e30f;
-        int best_kc = L.kc;
+        int best_kc = L.kc, best_remap = L.remapp[0];
         int64_t best_grid = L.grid;
         for (int kc : kcs)
-          for (int64_t gsz : grids) {
+          for (int64_t gsz : grids)
+            for (int remap = 0; remap < 2; ++remap) {
             if (gsz != 0 && gsz >= L.row_count) continue;
             if ((kc == kWaveRows || kc == kWaveTiles) && L.max_rows > 64) continue;
             if (kc == kWaveTiles && G.nvp != 32 && G.nvp != 64) continue;
+            if (remap && kc != kWaveRows && kc != kWaveTiles) continue;  // XCD ranges: wave-row kernels only
             Launch T = L;
             T.kc = kc;
             T.grid = gsz;
+            T.remapp[0] = remap;
             float tsum = 0.0f;
             for (int rep = 0; rep < 3; ++rep) {
               HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
@@ -498,10 +501,12 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
               best = tsum;
               best_kc = kc;
               best_grid = gsz;
+              best_remap = remap;
             }
           }
         L.kc = best_kc;
         L.grid = best_grid;
+        L.remapp[0] = best_remap;
       }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

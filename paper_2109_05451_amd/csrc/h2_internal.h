@@ -125,6 +125,9 @@ struct Plan {
   // the same rows in tree order (neighbouring rows share input segments), for
   // the multi-vector path when the tuner finds it faster
   std::vector<Launch> couple_loc, dense_loc, dense2_loc;
+  // the coupling rows split: the leaf level's (they need only the leaf
+  // products of the upsweep) and the other levels', longest first in each
+  std::vector<Launch> couple_deep, couple_rest;
   Launch out;                  // leaf expansion + dense partial + alpha/beta update
 };
 
@@ -253,6 +256,10 @@ struct Workspace {
   float* xh32 = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
+  // third stream of the multi-vector schedule 3: the leaf level's coupling
+  // rows beside the rest of the sweeps
+  hipStream_t side2 = nullptr;
+  hipEvent_t ev_deep = nullptr, ev_deep_done = nullptr;
 };
 int ws_create(Workspace* w, int64_t n, int64_t H, int64_t cap);
 // The product of h2_gemv_ex on an explicit workspace (w.n >= n, w.H >= H),
@@ -319,9 +326,12 @@ struct h2_op_s {
   float sweep_ms[3][2] = {};         // tuned times of the sweeps: per level, fused
   // multi-vector path, per precision: where the dense rows run (h2_tune):
   // 0 halves beside the upsweep and the downsweep, 1 the first half beside the
-  // coupling launch instead, 2 both halves from the start
+  // coupling launch instead, 2 both halves from the start, 3 both halves from
+  // the start and the leaf level's coupling rows on a third stream, beside
+  // the upsweep above the leaves, the other levels' coupling rows and the
+  // downsweep above the leaves
   int sched[3] = {0, 0, 0};
-  float sched_ms[3][3] = {};
+  float sched_ms[3][4] = {};
   int64_t index_bytes = 0;
   // the serialized header and index sections (bytes before U), 8-byte aligned,
   // and the representation's total size: the host view of the structure
@@ -338,7 +348,7 @@ struct h2_op_s {
   h2::Workspace na;
   // profiling
   bool profiling = false;
-  std::vector<std::array<hipEvent_t, 11>> ev_pool;
+  std::vector<std::array<hipEvent_t, 13>> ev_pool;
   size_t ev_used = 0;
   h2_profile_t prof{};
 };
@@ -388,12 +398,12 @@ hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double al
                                  int64_t ldy, int64_t n, int nv, int nvp, hipStream_t s);
 // The multi-vector row product with one wave per row (kc code kWaveRows of
 // the tuner), or one wave per 16-vector tile of a row (kWaveTiles); grid =
-// workgroups (0: enough for every row at once)
+// workgroups (0: enough for every row at once); remap: XCD-aware row ranges
 constexpr int kWaveRows = 9, kWaveTiles = 10;
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid, bool narrow = false);
+                            hipStream_t s, int64_t grid, bool narrow = false, int remap = 0);
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
                        const int32_t* colend, const int64_t* in_off, const T* data, double* const bufs[4], int nvp,

@@ -18,6 +18,8 @@
 // h2_kernels.hip (A[i][k] at lane i + 16k, B[k][j] at lane j + 16k, padded
 // steps reading zeros): the results are bitwise those of the per-level
 // launches.
+#include <algorithm>
+
 #include "h2_internal.h"
 
 namespace h2 {
@@ -170,14 +172,24 @@ template <typename T, int NT, int NTW, int MT>
 __global__ __launch_bounds__(kT) void k_wave_rows(const RowDesc* __restrict__ rows, int64_t nrows,
                                                   const int32_t* __restrict__ colend,
                                                   const int64_t* __restrict__ in_off, const T* __restrict__ data,
-                                                  const double* in, double* out, int mode) {
+                                                  const double* in, double* out, int mode, int remap) {
   constexpr int WPR = NT / NTW, RPW = 4 / WPR;
   __shared__ int32_t s_end[4][kNbMax];
   __shared__ int64_t s_in[4][kNbMax];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int slot = wave / WPR, vt0 = (wave % WPR) * NTW;
-  for (int64_t ri = (int64_t)blockIdx.x * RPW + slot; ri < nrows; ri += (int64_t)gridDim.x * RPW) {
+  // rows by workgroup: grid-stride, or (remap; a grid of a multiple of 8)
+  // each XCD (workgroups b with the same b % 8) takes one contiguous eighth
+  // of the rows, so that rows in flight together on an XCD are neighbours in
+  // the row order and their shared input segments meet in that XCD's L2
+  const int64_t per = remap ? (nrows + 7) / 8 : nrows;
+  const int64_t base = remap ? (int64_t)(blockIdx.x % 8) * per : 0;
+  const int64_t wg = remap ? blockIdx.x / 8 : blockIdx.x;
+  const int64_t nwg = remap ? gridDim.x / 8 : gridDim.x;
+  for (int64_t jr = wg * RPW + slot; jr < per; jr += nwg * RPW) {
+    const int64_t ri = base + jr;
+    if (ri >= nrows) break;
     const RowDesc R = rows[ri];
     const int nb = R.blk_end - R.blk_begin;  // <= kNbMax for rows of these tables
     __builtin_amdgcn_wave_barrier();         // the previous row's table fully read
@@ -254,10 +266,22 @@ hipError_t launch_permute_out_rm2(const double* Z, const double* Z2, const int32
   return hipGetLastError();
 }
 
+// Workgroups of a wave-row launch of rpw rows per workgroup pass: enough
+// for every row at once, or `grid`; with the XCD remap a multiple of 8
+// covering eight equal row ranges.
+inline int64_t wave_grid(int64_t nrows, int rpw, int64_t grid, int remap) {
+  if (!remap) {
+    const int64_t need = (nrows + rpw - 1) / rpw;
+    return grid > 0 && grid < need ? grid : need;
+  }
+  const int64_t per = (nrows + 7) / 8, needx = (per + rpw - 1) / rpw;
+  return grid > 0 ? std::min<int64_t>((grid + 7) / 8 * 8, 8 * needx) : 8 * needx;
+}
+
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid, bool narrow) {
+                            hipStream_t s, int64_t grid, bool narrow, int remap) {
   if (nrows == 0) return hipSuccess;
   if (max_rows > 64) return hipErrorInvalidValue;
   // narrow: a wave per 16-vector tile (NT waves per row, more waves resident); else a wave per row, or
@@ -266,17 +290,15 @@ hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* c
   do {                                                                                                   \
     if (narrow && (NT == 2 || NT == 4)) {                                                                \
       constexpr int RPWN = 4 / NT;                                                                       \
-      const int64_t needn = (nrows + RPWN - 1) / RPWN;                                                   \
-      const dim3 gn((unsigned)(grid > 0 && grid < needn ? grid : needn)), bn(kT);                        \
+      const dim3 gn((unsigned)wave_grid(nrows, RPWN, grid, remap)), bn(kT);                              \
       hipLaunchKernelGGL((k_wave_rows<T, NT, 1, MT>), gn, bn, 0, s, rows, nrows, colend, in_off, data, in, out, \
-                         mode);                                                                          \
+                         mode, remap);                                                                   \
       break;                                                                                             \
     }                                                                                                    \
     constexpr int NTW = (MT * NT > 8 && NT % 2 == 0) ? NT / 2 : NT, RPW = 4 / (NT / NTW);               \
-    const int64_t need = (nrows + RPW - 1) / RPW;                                                        \
-    const dim3 g((unsigned)(grid > 0 && grid < need ? grid : need)), b(kT);                              \
+    const dim3 g((unsigned)wave_grid(nrows, RPW, grid, remap)), b(kT);                                   \
     hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT>), g, b, 0, s, rows, nrows, colend, in_off, data, in, out, \
-                       mode);                                                                            \
+                       mode, remap);                                                                     \
   } while (0)
 #define H2_WR_NT(NT)                          \
   do {                                        \
@@ -297,9 +319,9 @@ hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* c
   return hipGetLastError();
 }
 template hipError_t launch_wave_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
-                                             const double*, double*, int, int, int, hipStream_t, int64_t, bool);
+                                             const double*, double*, int, int, int, hipStream_t, int64_t, bool, int);
 template hipError_t launch_wave_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
-                                            const double*, double*, int, int, int, hipStream_t, int64_t, bool);
+                                            const double*, double*, int, int, int, hipStream_t, int64_t, bool, int);
 
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
