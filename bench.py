@@ -130,6 +130,25 @@ def coupling_roofline(st: dict, nv: int, precision: str, t_ms: float, config: st
     return out
 
 
+def tuned_coupling_ms(info: str, precision: str):
+    """The coupling rows' standalone time (ms per product) that the autotuner
+    measured for the kernel form it kept, from the plan description: the
+    one coupling launch in the row order it chose, or under schedule 3 the
+    leaf-level launch plus the other levels' launch.  None if untuned."""
+    import re
+    sched = re.search(precision + r": dense schedule (\d)", info)
+    tree = re.search(precision + r": coupling rows tree order", info) is not None
+    names = ("couple_deep", "couple_rest") if sched and sched.group(1) == "3" else (
+        ("couple_tree",) if tree else ("couple",))
+    total = 0.0
+    for nm in names:
+        m = re.search(r"^" + nm + r" rows=.*?\| " + precision + r" kc=\S+ grid=\S+ xcd=\S+ ([0-9.]+)ms", info, re.M)
+        if not m or float(m.group(1)) <= 0.0:
+            return None
+        total += float(m.group(1))
+    return total
+
+
 def sample_rows(n: int, seed: int, count: int = 192) -> np.ndarray:
     """Output rows whose values the oracle computes one by one (both ends,
     the middle and a seeded uniform sample)."""
@@ -745,6 +764,8 @@ def run_workload(name, runs, args, torch, latency_for=None):
             res.update(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)), lat_samples=lat.size)
         if v <= 4 and prec == "fp64":
             res["launches"] = launches_per_product(g)
+        if v > 4 or prec == "bf16":
+            res["couple_alone_ms"] = tuned_coupling_ms(g.plan_info(), prec)
         res["got_rows"] = Y.index_select(0, rows_dev).cpu().numpy()
         res["finite"] = bool(torch.isfinite(Y).all().item())
         results[(v, prec)] = res
@@ -756,12 +777,20 @@ def run_workload(name, runs, args, torch, latency_for=None):
 
 
 def variant_record(name, st, v, prec, res) -> dict:
+    roof = coupling_roofline(st, v, prec, res["prof"]["coupling"], name)
+    alone = res.get("couple_alone_ms")
+    if alone:
+        # the same launch(es) timed alone by the autotuner: inside the product
+        # the dense rows run beside them and stretch their interval
+        ra = coupling_roofline(st, v, prec, alone)
+        roof.update({"ms_per_launch_alone": round(alone, 4), "achieved_alone": ra["achieved"],
+                     "frac_alone": ra["frac"]})
     return {"workload": name, "nv": v, "precision": prec, "ms": round(res["t_ms"], 4),
             "gflops": round(res["alg"]["flops"] / (res["t_ms"] * 1e-3) / 1e9, 2),
             "gb_per_s_fp64_equiv": round(res["alg"]["bytes"] / (res["t_ms"] * 1e-3) / 1e9, 1),
             "rel_err_vs_oracle": res.get("rel_err"), "max_err_over_B": res.get("err_over_B"),
             "finite": res["finite"], "p99_ms": round(res["p99"], 4),
-            "roofline": coupling_roofline(st, v, prec, res["prof"]["coupling"], name),
+            "roofline": roof,
             "path_roofline": path_roofline(st, v, prec, res["t_ms"]),
             "phases_ms": res["prof"]}
 
