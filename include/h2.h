@@ -394,9 +394,13 @@ int h2_batch_load_ex(const void* const* bufs, const size_t* lens, int64_t count,
 int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream);
 
 /* Autotuner: for every merged launch, time each candidate shape (columns
- * staged per LDS chunk: 32 or 64, or one wave per row with no LDS staging;
+ * staged per LDS chunk: 32 or 64, or one wave per row or per 16-vector tile
+ * with no LDS staging, the latter two also with XCD-aware row ranges;
  * workgroups: one per row (four rows for the wave form) or a persistent grid
- * of 1024, 2048 or 4096) on these items and keep the fastest.
+ * of 1024, 2048 or 4096) on these items and keep the fastest; then time
+ * whole calls with the dense rows on the second stream from the start
+ * (beside the upsweep) or from the end of the upsweep (beside the coupling
+ * launches) and keep the faster.  Results do not depend on the choices.
  * Synchronous; the workspace content afterwards is unspecified. */
 int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream);
 

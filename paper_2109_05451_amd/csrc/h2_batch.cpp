@@ -77,6 +77,11 @@ struct h2_batch_s {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_items = nullptr;
   bool items_pending = false;
+  // where the dense rows run (h2_batch_tune): 0 on the second stream from the
+  // start, beside the upsweep; 1 on the second stream after the upsweep,
+  // beside the coupling launches
+  int sched = 0;
+  float sched_ms[2] = {0.0f, 0.0f};
   bool use_graph = false;
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
@@ -297,12 +302,18 @@ int batch_sequence(h2_batch_s* b, hipStream_t s) {
   for (const Group& G : b->groups)
     HIP_TRYB(launch_batch_permute(b->d_items, G.d_tile_op, G.d_tile_j0, G.ntiles, b->d_pinv, G.d_ws, G.nvp, false, s),
              "batch permute");
-  HIP_TRYB(hipEventRecord(b->ev_fork, s), "hipEventRecord");
-  HIP_TRYB(hipStreamWaitEvent(b->side, b->ev_fork, 0), "hipStreamWaitEvent");
-  if ((rc = run_phase(b, &Group::dense, nullptr, -1, b->side))) return rc;
-  HIP_TRYB(hipEventRecord(b->ev_join, b->side), "hipEventRecord");
+  auto fork_dense = [&]() -> int {
+    HIP_TRYB(hipEventRecord(b->ev_fork, s), "hipEventRecord");
+    HIP_TRYB(hipStreamWaitEvent(b->side, b->ev_fork, 0), "hipStreamWaitEvent");
+    int r = run_phase(b, &Group::dense, nullptr, -1, b->side);
+    if (r != H2_OK) return r;
+    HIP_TRYB(hipEventRecord(b->ev_join, b->side), "hipEventRecord");
+    return H2_OK;
+  };
+  if (b->sched == 0 && (rc = fork_dense())) return rc;
   for (int64_t h = 0; h <= b->maxq; ++h)
     if ((rc = run_phase(b, &Group::up, &Group::up_level, h, s))) return rc;
+  if (b->sched == 1 && (rc = fork_dense())) return rc;
   if ((rc = run_phase(b, &Group::couple, nullptr, -1, s))) return rc;
   for (int64_t d = 0; d < b->maxq; ++d)
     if ((rc = run_phase(b, &Group::down, &Group::down_level, d, s))) return rc;
@@ -508,6 +519,23 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
         L.grid = best_grid;
         L.remapp[0] = best_remap;
       }
+  // the dense rows' schedule, on whole launch sequences (a warm-up, then two
+  // timed runs each)
+  for (int sc = 0; sc < 2; ++sc) {
+    b->sched = sc;
+    float t = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
+      if ((rc = batch_sequence(b, s))) return rc;
+      HIP_TRYB(hipEventRecord(e1, s), "hipEventRecord");
+      HIP_TRYB(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.0f;
+      HIP_TRYB(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (rep > 0) t += ms;
+    }
+    b->sched_ms[sc] = t / 2;
+  }
+  b->sched = b->sched_ms[1] < b->sched_ms[0] ? 1 : 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->use_graph = graph_was;
