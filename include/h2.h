@@ -216,8 +216,9 @@ int h2_reserve(h2_handle h, int64_t nv_max);
  * h2_set_schedule are timed on whole products (zeroed input) and the
  * fastest is kept.
  * Results do not depend on the choice: every candidate sums each output in
- * the same order, so they are bitwise identical.  No-op for nv <= 4 outside
- * BF16 (the streaming kernel has nothing to tune).  Synchronous; must not run concurrently with other calls on the
+ * the same order, so they are bitwise identical.  For nv <= 4 outside BF16
+ * (the streaming path) it times the four schedules of h2_set_schedule on
+ * whole products and keeps the fastest.  Synchronous; must not run concurrently with other calls on the
  * handle (it uses the handle's workspace).
  * Errors: H2_EINVAL (null handle, nv < 0, unknown precision), H2_ENOMEM,
  * H2_EHIP. */
@@ -292,8 +293,10 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
  * Errors: H2_EINVAL. */
 int h2_set_dense_grid(h2_handle h, int64_t workgroups);
 
-/* Where the multi-vector path (op 'N', more than 4 vectors, or BF16) runs
- * its dense near-field rows and its coupling rows, for precision `prec`:
+/* Where the product of op 'N' runs its dense near-field rows and its
+ * coupling rows, for precision `prec` (on the multi-vector path, more than 4
+ * vectors or BF16, and on the streaming path; h2_tune tunes each path on
+ * its own):
  *   0  the dense rows' first half on a second stream beside the upsweep, the
  *      second half beside the downsweep and the leaf expansion
  *   1  the first half beside the coupling launch instead

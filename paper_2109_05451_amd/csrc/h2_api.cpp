@@ -749,7 +749,7 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   // and the leaf level's coupling rows on a third stream as soon as the leaf
   // products are done, beside the upper upsweep, the other levels' coupling
   // rows and the upper downsweep (the last downsweep level waits for them).
-  const int sched = nvp > 0 && !trans ? h->sched[pidx] : 0;
+  const int sched = trans ? 0 : nvp > 0 ? h->sched[pidx] : h->sched1[pidx];
   const bool fused = use_tree(h, w, trans, nvp, prec);
   // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
   const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
@@ -995,6 +995,68 @@ int check_gemv_args(h2_op_s* h, char op, double alpha, const double* X, int64_t 
 }
 }  // namespace h2
 
+namespace {
+// Streaming products (nv <= kPassVectors): the four schedules of
+// h2_set_schedule timed on whole products (a warm-up, then three runs each)
+// on zeroed buffers; the fastest is kept.
+int tune_stream_schedule(h2_op_s* h, int64_t nv, int prec, void* stream) {
+  if (nv == 0) return H2_OK;
+  DeviceGuard guard(h->device);
+  if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
+  int rc;
+  if ((rc = h2_prepare(h, prec)) != H2_OK) return rc;
+  if ((rc = ensure_workspace(h, nv)) != H2_OK) return rc;
+  const int nvc = (int)std::min<int64_t>(nv, kPassVectors);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *X = nullptr, *Y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t vb = sizeof(double) * (size_t)std::max<int64_t>(h->n, 1) * nvc;
+  auto done = [&](int r) {
+    if (X) (void)hipFree(X);
+    if (Y) (void)hipFree(Y);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return r;
+  };
+  if (hipMalloc(reinterpret_cast<void**>(&X), vb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&Y), vb) != hipSuccess || hipMemsetAsync(X, 0, vb, s) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("tuning buffers");
+    return done(H2_ENOMEM);
+  }
+  float best = 1e30f;
+  int best_s = h->sched1[prec];
+  for (int sc = 0; sc < 4; ++sc) {
+    h->sched1[prec] = sc;
+    float t = 0.0f;
+    for (int rep = 0; rep < 4; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) return done(H2_EHIP);
+      if ((rc = gemv_ws(h, h->ws, false, 1.0, X, h->n, nvc, 0.0, Y, h->n, prec, s)) != H2_OK) {
+        h->sched1[prec] = best_s;
+        return done(rc);
+      }
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        h->sched1[prec] = best_s;
+        set_error("timing the streaming schedules failed");
+        return done(H2_EHIP);
+      }
+      if (rep > 0) t += ms;
+    }
+    h->sched1_ms[prec][sc] = t / 3;
+    if (t < best) {
+      best = t;
+      best_s = sc;
+    }
+  }
+  h->sched1[prec] = best_s;
+  return done(H2_OK);
+}
+}  // namespace
+
 extern "C" {
 int h2_gemv_ex(h2_handle h, char op, double alpha, const double* X, int64_t ldx, int64_t nv, double beta,
                double* Y, int64_t ldy, int prec, void* stream) {
@@ -1082,7 +1144,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     set_error("unknown precision");
     return H2_EINVAL;
   }
-  if (nv <= kPassVectors && prec != H2_PREC_BF16) return H2_OK;  // streaming path: nothing to tune
+  if (nv <= kPassVectors && prec != H2_PREC_BF16) return tune_stream_schedule(h, nv, prec, stream);
   DeviceGuard guard(h->device);
   if (!guard.ok) { set_error("hipSetDevice failed"); return H2_EHIP; }
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -1311,6 +1373,7 @@ int h2_set_schedule(h2_handle h, int prec, int schedule) {
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
   drop_graphs(h);
   h->sched[prec] = schedule;
+  h->sched1[prec] = schedule;
   return H2_OK;
 }
 
@@ -1360,6 +1423,10 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
   for (int p = 0; p < 3; ++p) {
     std::snprintf(line, sizeof line, "%s: dense schedule %d (tuned products %.3f / %.3f / %.3f / %.3f ms)\n",
                   pn[p], h->sched[p], h->sched_ms[p][0], h->sched_ms[p][1], h->sched_ms[p][2], h->sched_ms[p][3]);
+    t += line;
+    std::snprintf(line, sizeof line,
+                  "%s: streaming dense schedule %d (tuned products %.3f / %.3f / %.3f / %.3f ms)\n", pn[p],
+                  h->sched1[p], h->sched1_ms[p][0], h->sched1_ms[p][1], h->sched1_ms[p][2], h->sched1_ms[p][3]);
     t += line;
   }
   for (const auto* v : {&h->tree_up, &h->tree_down})

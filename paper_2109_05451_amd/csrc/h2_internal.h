@@ -332,6 +332,10 @@ struct h2_op_s {
   // downsweep above the leaves
   int sched[3] = {0, 0, 0};
   float sched_ms[3][4] = {};
+  // the same choice for the streaming path (at most 4 vectors per pass; FP64
+  // and FP32), tuned separately
+  int sched1[3] = {0, 0, 0};
+  float sched1_ms[3][4] = {};
   int64_t index_bytes = 0;
   // the serialized header and index sections (bytes before U), 8-byte aligned,
   // and the representation's total size: the host view of the structure

@@ -53,3 +53,33 @@ def test_schedules_bitwise(dim):
                 assert np.all(np.abs(results[0][1] - want) <= 1e-12 * B), (dim, nv)
     g.close()
     ref.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_streaming_schedules_bitwise(dim):
+    """The same four schedules on the streaming path (1 to 4 vectors): equal
+    bits across schedules and after tuning, the oracle's within 1e-12 * B."""
+    from paper_2109_05451_amd import H2Operator
+    if dim == 2:
+        buf = np.array(h2gen.build(h2gen.points(9000, 2, 23), leaf=64, p=6, eta=0.7, kernel="exp").array, copy=True)
+    else:
+        buf = np.array(h2gen.build(h2gen.points(7000, 3, 24), leaf=64, p=4, eta=0.7, kernel="laplace").array,
+                       copy=True)
+    ref = oracle.Oracle(buf)
+    g = H2Operator(buf)
+    for nv in (1, 3):
+        X = h2gen.vectors(g.n, nv, 50 + nv)
+        want, B = ref.gemv(X), ref.gemv(X, absval=True)
+        for prec in ("fp64", "fp32"):
+            results = []
+            for sc in (0, 1, 2, 3):
+                g.set_schedule(prec, sc)
+                results.append(run(g, X, prec))
+            g.tune(nv, prec)
+            results.append(run(g, X, prec))
+            for k, r in enumerate(results[1:]):
+                assert np.array_equal(r, results[0]), (dim, nv, prec, k + 1)
+            if prec == "fp64":
+                assert np.all(np.abs(results[0] - want) <= 1e-12 * B), (dim, nv)
+    g.close()
+    ref.close()
