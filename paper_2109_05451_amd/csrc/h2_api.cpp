@@ -753,8 +753,10 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
   const bool fused = use_tree(h, w, trans, nvp, prec);
   // FP32 at 64 vectors: the coupling launches gather x^ from an FP32 copy
   const bool x32 = prec == H2_PREC_FP32 && nvp == kPassVectorsMfma && w.xh32;
+  // (a workspace without the third stream, such as the no-allocation
+  // product's views, takes schedule 2's order instead)
   const bool split = sched == 3 && !fused && !x32 && !plan.down.empty() && !plan.couple_deep.empty() &&
-                     !plan.up.empty();
+                     !plan.up.empty() && w.side2 && w.ev_deep && w.ev_deep_done;
   auto fork_dense1 = [&]() -> int {
     HIP_TRY(hipEventRecord(w.ev_fork, s), "hipEventRecord(fork)");
     HIP_TRY(hipStreamWaitEvent(w.side, w.ev_fork, 0), "hipStreamWaitEvent(fork)");

@@ -100,3 +100,22 @@ def test_noalloc_narrow_passes_2d_2e20():
             assert np.array_equal(na, al)
     g.close()
     ref.close()
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3])
+def test_noalloc_under_every_schedule(schedule):
+    """The no-allocation product follows the handle's schedule on its own
+    side stream (schedule 3, which needs a third stream that the fixed
+    scratch views do not have, runs as schedule 2): with passes of the same
+    width as h2_gemv it gives h2_gemv's bits."""
+    from paper_2109_05451_amd import H2Operator
+    buf = np.array(h2gen.build_config("c1_2d_4096").array, copy=True)
+    g = H2Operator(buf)
+    g.set_schedule("fp64", schedule)
+    rng = np.random.default_rng(30 + schedule)
+    for nv in (1, 3):
+        X = rng.standard_normal((g.n, nv))
+        Y0 = rng.standard_normal((g.n, nv))
+        na, al = both(g, X, Y0, "N", 1.0, 0.5)
+        assert np.array_equal(na, al), (schedule, nv)
+    g.close()
