@@ -2,8 +2,9 @@
 the eager product bit for bit, with the input buffer refilled between
 replays (X is read at replay time), eager work and synchronizations between
 replays, a second set of buffers captured separately, retuning dropping the
-graphs, and both the streaming (1 vector) and multi-vector (20 vectors,
-FP64 and FP32) paths; the eager products are the oracle's within the bars of
+graphs, both the streaming (1 vector) and multi-vector (20 vectors, FP64 and
+FP32) paths, and schedules 0 and 3 (the latter forks a third stream inside
+the capture); the eager products are the oracle's within the bars of
 the other parity tests."""
 import numpy as np
 import pytest
@@ -19,13 +20,15 @@ def product(g, X, Y, nv, prec, stream, alpha=1.5, beta=-0.5):
     g.gemv_raw("N", alpha, X.data_ptr(), g.n, nv, beta, Y.data_ptr(), g.n, stream.cuda_stream, prec)
 
 
+@pytest.mark.parametrize("schedule", [0, 3])
 @pytest.mark.parametrize("nv,prec", [(1, "fp64"), (1, "fp32"), (20, "fp64"), (20, "fp32")])
-def test_graph_replays_match_eager(nv, prec):
+def test_graph_replays_match_eager(nv, prec, schedule):
     from paper_2109_05451_amd import H2Operator
     buf = np.array(h2gen.build_config("c1_2d_4096").array, copy=True)
     ref = oracle.Oracle(buf)
     g = H2Operator(buf)
     g.prepare("fp32")
+    g.set_schedule(prec, schedule)  # 3: a third stream forked into and joined back from the capture
     n = g.n
     stream = torch.cuda.Stream()
     rng = np.random.default_rng(nv)
@@ -70,6 +73,7 @@ def test_graph_replays_match_eager(nv, prec):
     assert np.array_equal(Y2.cpu().numpy(), eager[1])
     # retuning drops the graphs; the next call captures afresh
     g.tune(64 if nv > 4 else 1, prec)
+    g.set_schedule(prec, schedule)
     X.copy_(torch.from_numpy(inputs[2]))
     Y.copy_(torch.from_numpy(Y0))
     torch.cuda.synchronize()
