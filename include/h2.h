@@ -403,7 +403,9 @@ int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream);
  * of 1024, 2048 or 4096) on these items and keep the fastest; then time
  * whole calls with the dense rows on the second stream from the start
  * (beside the upsweep) or from the end of the upsweep (beside the coupling
- * launches) and keep the faster.  Results do not depend on the choices.
+ * launches), and with each vector-width group's sweeps and coupling rows on
+ * a stream of its own, and keep the fastest.  Results do not depend on the
+ * choices.
  * Synchronous; the workspace content afterwards is unspecified. */
 int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream);
 

@@ -57,6 +57,10 @@ struct Group {
   std::vector<int64_t> up_level, down_level;         // the merged level of each launch
   int32_t *d_tile_op = nullptr, *d_tile_j0 = nullptr;
   int64_t ntiles = 0;
+  // groups after the first: their own stream for the sweeps and coupling
+  // rows when the groups run side by side (h2_batch_s::par)
+  hipStream_t st = nullptr;
+  hipEvent_t ev_go = nullptr, ev_done = nullptr;
 };
 
 }  // namespace
@@ -81,7 +85,11 @@ struct h2_batch_s {
   // start, beside the upsweep; 1 on the second stream after the upsweep,
   // beside the coupling launches
   int sched = 0;
-  float sched_ms[2] = {0.0f, 0.0f};
+  // par: each vector-width group's sweeps and coupling rows on a stream of
+  // its own (the groups are independent operators), the dense rows beside
+  // them from the start; else the groups' launches interleaved on one stream
+  bool par = false;
+  float sched_ms[3] = {0.0f, 0.0f, 0.0f};
   bool use_graph = false;
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
@@ -94,6 +102,9 @@ void free_batch(h2_batch_s* b) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   F(b->d_mat); F(b->d_trans); F(b->d_pinv); F(b->d_items);
   for (Group& g : b->groups) {
+    if (g.ev_go) (void)hipEventDestroy(g.ev_go);
+    if (g.ev_done) (void)hipEventDestroy(g.ev_done);
+    if (g.st) (void)hipStreamDestroy(g.st);
     F(g.d_ws); F(g.d_tile_op); F(g.d_tile_j0);
   }
   F(b->rt.d_rows); F(b->rt.d_colend); F(b->rt.d_in_off);
@@ -260,6 +271,12 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
            "hipHostMalloc(items)");
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_items), sizeof(BatchItem) * count), "hipMalloc(items)");
   HIP_TRYB(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "hipStreamCreate");
+  for (size_t gi = 1; gi < b->groups.size(); ++gi) {
+    Group& G = b->groups[gi];
+    HIP_TRYB(hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRYB(hipEventCreateWithFlags(&G.ev_go, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRYB(hipEventCreateWithFlags(&G.ev_done, hipEventDisableTiming), "hipEventCreate");
+  }
   HIP_TRYB(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "hipEventCreate");
   HIP_TRYB(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "hipEventCreate");
   HIP_TRYB(hipEventCreateWithFlags(&b->ev_items, hipEventDisableTiming), "hipEventCreate");
@@ -310,13 +327,39 @@ int batch_sequence(h2_batch_s* b, hipStream_t s) {
     HIP_TRYB(hipEventRecord(b->ev_join, b->side), "hipEventRecord");
     return H2_OK;
   };
-  if (b->sched == 0 && (rc = fork_dense())) return rc;
-  for (int64_t h = 0; h <= b->maxq; ++h)
-    if ((rc = run_phase(b, &Group::up, &Group::up_level, h, s))) return rc;
-  if (b->sched == 1 && (rc = fork_dense())) return rc;
-  if ((rc = run_phase(b, &Group::couple, nullptr, -1, s))) return rc;
-  for (int64_t d = 0; d < b->maxq; ++d)
-    if ((rc = run_phase(b, &Group::down, &Group::down_level, d, s))) return rc;
+  if (b->par && b->groups.size() > 1) {
+    if ((rc = fork_dense())) return rc;
+    // one stream per group: its upsweep, coupling rows and downsweep; every
+    // group's stream forks from this point of the main stream, before the
+    // first group's launches are queued on it
+    for (size_t gi = 1; gi < b->groups.size(); ++gi) {
+      HIP_TRYB(hipEventRecord(b->groups[gi].ev_go, s), "hipEventRecord");
+      HIP_TRYB(hipStreamWaitEvent(b->groups[gi].st, b->groups[gi].ev_go, 0), "hipStreamWaitEvent");
+    }
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const Group& G = b->groups[gi];
+      hipStream_t gs = gi == 0 ? s : G.st;
+      for (int64_t h = 0; h <= b->maxq; ++h)
+        for (size_t k = 0; k < G.up.size(); ++k)
+          if (G.up_level[k] == h && (rc = run_blaunch(b, G, G.up[k], gs))) return rc;
+      for (const Launch& L : G.couple)
+        if ((rc = run_blaunch(b, G, L, gs))) return rc;
+      for (int64_t d = 0; d < b->maxq; ++d)
+        for (size_t k = 0; k < G.down.size(); ++k)
+          if (G.down_level[k] == d && (rc = run_blaunch(b, G, G.down[k], gs))) return rc;
+      if (gi > 0) HIP_TRYB(hipEventRecord(G.ev_done, gs), "hipEventRecord");
+    }
+    for (size_t gi = 1; gi < b->groups.size(); ++gi)
+      HIP_TRYB(hipStreamWaitEvent(s, b->groups[gi].ev_done, 0), "hipStreamWaitEvent");
+  } else {
+    if (b->sched == 0 && (rc = fork_dense())) return rc;
+    for (int64_t h = 0; h <= b->maxq; ++h)
+      if ((rc = run_phase(b, &Group::up, &Group::up_level, h, s))) return rc;
+    if (b->sched == 1 && (rc = fork_dense())) return rc;
+    if ((rc = run_phase(b, &Group::couple, nullptr, -1, s))) return rc;
+    for (int64_t d = 0; d < b->maxq; ++d)
+      if ((rc = run_phase(b, &Group::down, &Group::down_level, d, s))) return rc;
+  }
   HIP_TRYB(hipStreamWaitEvent(s, b->ev_join, 0), "hipStreamWaitEvent");
   if ((rc = run_phase(b, &Group::out, nullptr, -1, s))) return rc;
   for (const Group& G : b->groups)
@@ -521,8 +564,9 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
       }
   // the dense rows' schedule, on whole launch sequences (a warm-up, then two
   // timed runs each)
-  for (int sc = 0; sc < 2; ++sc) {
-    b->sched = sc;
+  for (int sc = 0; sc < 3; ++sc) {  // dense from the start; after the upsweep; groups side by side
+    b->sched = sc == 1 ? 1 : 0;
+    b->par = sc == 2;
     float t = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
       HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
@@ -535,7 +579,11 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
     }
     b->sched_ms[sc] = t / 2;
   }
-  b->sched = b->sched_ms[1] < b->sched_ms[0] ? 1 : 0;
+  int best = 0;
+  for (int sc = 1; sc < 3; ++sc)
+    if (b->sched_ms[sc] < b->sched_ms[best]) best = sc;
+  b->sched = best == 1 ? 1 : 0;
+  b->par = best == 2;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->use_graph = graph_was;
