@@ -1244,11 +1244,10 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if (rc == H2_OK) rc = tune_list(plan.down, &t_down);
   if (rc == H2_OK) rc = tune_list(plan.couple, &tc, true);
   if (rc == H2_OK) rc = tune_list(plan.couple_loc, &tcl, true);
-  float tcd = 0, tcr = 0;
-  if (rc == H2_OK) rc = tune_list(plan.couple_deep, &tcd, true);
-  if (rc == H2_OK) rc = tune_list(plan.couple_rest, &tcr, true);
-  (void)tcd;
-  (void)tcr;
+  // the split coupling rows of schedule 3 (their times are not compared)
+  for (auto* v : {&plan.couple_deep, &plan.couple_rest})
+    for (Launch& L : *v)
+      if (rc == H2_OK) rc = tune_one(L, -1, nullptr, true);
   if (rc == H2_OK) rc = tune_list(plan.dense, &td1);
   if (rc == H2_OK) rc = tune_list(plan.dense2, &td2);
   if (rc == H2_OK) rc = tune_list(plan.dense_loc, &tl1);
