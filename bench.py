@@ -142,7 +142,8 @@ def tuned_coupling_ms(info: str, precision: str):
         ("couple_tree",) if tree else ("couple",))
     total = 0.0
     for nm in names:
-        m = re.search(r"^" + nm + r" rows=.*?\| " + precision + r" kc=\S+ grid=\S+ xcd=\S+ ([0-9.]+)ms", info, re.M)
+        m = re.search(r"^" + nm + r" rows=.*?\| " + precision + r" kc=\S+ grid=\S+ xcd=\S+ (?:fl=\S+ )?([0-9.]+)ms",
+                      info, re.M)
         if not m or float(m.group(1)) <= 0.0:
             return None
         total += float(m.group(1))

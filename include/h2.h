@@ -205,9 +205,15 @@ int h2_prepare(h2_handle h, int prec);
 int h2_reserve(h2_handle h, int64_t nv_max);
 
 /* Autotune the multi-vector (MFMA) path of op 'N' for `nv` vectors in
- * precision `prec`: for every launch of the product, each candidate kernel
- * form (the h2_tune_set codes; BF16 has one form) and grid (one workgroup per
- * row, or a persistent grid of 1024, 2048 or 4096 workgroups) is timed with
+ * precision `prec`: first it makes the fragment-ordered copy of the op-'N'
+ * rows' matrices (FP64 for every row; for FP32 also of the low-rank rows, in
+ * FP32; device memory about the size of the matrix data, once per handle):
+ * each row's matrix reordered so that a wave of the wave-row kernels reads
+ * its MFMA operands of two four-column steps as whole 128-byte lines.  Then,
+ * for every launch of the product, each candidate kernel form (the
+ * h2_tune_set codes; the wave-row forms with and without the copy; BF16 has
+ * one form) and grid (one workgroup per row, or a persistent grid of 1024,
+ * 2048 or 4096 workgroups) is timed with
  * HIP events on `stream` (three runs, the first discarded) on zeroed
  * workspace buffers, and the fastest is kept for later calls in that
  * precision (the dense rows, always FP64, keep theirs in the FP64 entry);
@@ -321,10 +327,20 @@ int h2_set_schedule(h2_handle h, int prec, int schedule);
  * H2_EUNSUPPORTED (fused asked for, but the operator has longer rows). */
 int h2_set_sweeps(h2_handle h, int prec, int fused);
 
+/* enable != 0: make the fragment-ordered copy of the rows' matrices for
+ * precision `prec` now (see h2_tune) and let every wave-row launch of that
+ * precision read it (the dense rows' FP64 entries too); enable == 0: read
+ * the column-major data, and free copies that no launch reads any more.
+ * Results are bitwise the same either way; h2_tune chooses per launch.
+ * Errors: H2_EINVAL (null handle, precision other than FP64 or FP32),
+ * H2_ENOMEM, H2_EHIP. */
+int h2_set_fragment_order(h2_handle h, int prec, int enable);
+
 /* A text description of the op-'N' launch plan and its tuned parameters
- * (row order per precision; per launch: rows, chunk width, grid, XCD mapping
- * per precision), NUL-terminated, truncated to `cap` bytes; *needed receives
- * the full size.  Errors: H2_EINVAL. */
+ * (row order per precision; per launch: rows, chunk width, grid, XCD mapping,
+ * fragment-ordered copy and tuned time per precision), NUL-terminated,
+ * truncated to `cap` bytes; *needed receives the full size.
+ * Errors: H2_EINVAL. */
 int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed);
 
 /* Fill *st with the operator's structure and stored-entry counts. */
@@ -417,6 +433,13 @@ int h2_batch_graph(h2_batch b, int enable);
 /* Number of operators, total order sum n_i, algorithmic flops per vector
  * (2 * stored entries of all parts) and merged launches per call. */
 int h2_batch_info(h2_batch b, int64_t* count, int64_t* total_n, double* flops_per_vector, int64_t* launches);
+
+/* A text description of the batch's launch plan: the whole-call schedule
+ * with the tuned call times, then per vector-width group and merged launch
+ * the phase, rows, largest row, kernel form, grid, XCD mapping and tuned
+ * time.  NUL-terminated, truncated to `cap` bytes; *needed receives the full
+ * size.  Errors: H2_EINVAL. */
+int h2_batch_plan_info(h2_batch b, char* buf, size_t cap, size_t* needed);
 
 /* Release the batch (synchronizes the device first); NULL is a no-op. */
 int h2_batch_free(h2_batch b);

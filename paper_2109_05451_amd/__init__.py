@@ -21,8 +21,8 @@ H2_OK, H2_EINVAL, H2_EIO, H2_EFORMAT, H2_ENOMEM, H2_EHIP, H2_EUNSUPPORTED = 0, -
 # exported symbols of include/h2.h, in declaration order
 EXPORTS = ("h2_load", "h2_load_mem", "h2_validate", "h2_gemv", "h2_gemv_ex", "h2_gemv_noalloc", "h2_graph", "h2_prepare", "h2_reserve", "h2_tune",
            "h2_compress", "h2_export", "h2_ranks", "h2_plan_info", "h2_tune_set", "h2_set_dense_grid", "h2_set_schedule",
-           "h2_set_sweeps", "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_load_ex", "h2_batch_gemv",
-           "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_free", "h2_server_create",
+           "h2_set_sweeps", "h2_set_fragment_order", "h2_stats", "h2_level_stats", "h2_n", "h2_profile", "h2_profile_read", "h2_free", "h2_batch_load", "h2_batch_load_ex", "h2_batch_gemv",
+           "h2_batch_tune", "h2_batch_graph", "h2_batch_info", "h2_batch_plan_info", "h2_batch_free", "h2_server_create",
            "h2_server_submit", "h2_server_wait", "h2_server_stats", "h2_server_free", "h2_last_error")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
@@ -132,6 +132,8 @@ def load_library(path: str = LIB_PATH):
     lib.h2_set_dense_grid.restype = ci
     lib.h2_set_sweeps.argtypes = [vp, ci, ci]
     lib.h2_set_sweeps.restype = ci
+    lib.h2_set_fragment_order.argtypes = [vp, ci, ci]
+    lib.h2_set_fragment_order.restype = ci
     lib.h2_set_schedule.argtypes = [vp, ci, ci]
     lib.h2_set_schedule.restype = ci
     lib.h2_stats.argtypes = [vp, ctypes.POINTER(H2Stats)]
@@ -159,6 +161,8 @@ def load_library(path: str = LIB_PATH):
     lib.h2_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                   ctypes.POINTER(i64)]
     lib.h2_batch_info.restype = ci
+    lib.h2_batch_plan_info.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.h2_batch_plan_info.restype = ci
     lib.h2_batch_free.argtypes = [vp]
     lib.h2_batch_free.restype = ci
     lib.h2_server_create.argtypes = [ctypes.POINTER(vp), i64, i64, i64, i64, ctypes.POINTER(vp)]
@@ -257,6 +261,10 @@ class H2Operator:
     def set_sweeps(self, precision: str = "fp64", fused: bool = True):
         """Fused subtree sweeps or one launch per level (see h2_set_sweeps)."""
         _check(load_library().h2_set_sweeps(self._h, PRECISIONS[precision], 1 if fused else 0))
+
+    def set_fragment_order(self, precision: str = "fp64", enable: bool = True):
+        """Wave-row launches read the fragment-ordered matrix copy (see h2_set_fragment_order)."""
+        _check(load_library().h2_set_fragment_order(self._h, PRECISIONS[precision], 1 if enable else 0))
 
     def plan_info(self) -> str:
         """Text description of the launch plan and its tuned parameters."""
@@ -404,6 +412,15 @@ class H2Batch:
         _check(load_library().h2_batch_info(self._h, ctypes.byref(c), ctypes.byref(n), ctypes.byref(f),
                                             ctypes.byref(l)))
         return {"count": c.value, "total_n": n.value, "flops_per_vector": f.value, "launches": l.value}
+
+    def plan_info(self) -> str:
+        """Text description of the merged launches and their tuned parameters."""
+        lib = load_library()
+        need = ctypes.c_size_t()
+        _check(lib.h2_batch_plan_info(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.h2_batch_plan_info(self._h, buf, need.value, ctypes.byref(need)))
+        return buf.value.decode()
 
     @staticmethod
     def _items(Xs, Ys, alphas, betas):

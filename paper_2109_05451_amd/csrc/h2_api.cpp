@@ -146,7 +146,7 @@ void free_device(h2_op_s* h) {
   drop_graphs(h);
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   F(h->d_mat); F(h->d_trans); F(h->d_perm); F(h->d_pinv); F(h->d_mat32); F(h->d_trans32);
-  F(h->d_mat16); F(h->d_trans16);
+  F(h->d_mat16); F(h->d_trans16); F(h->d_fl); F(h->d_fl32);
   F(h->rt.d_rows); F(h->rt.d_colend); F(h->rt.d_in_off);
   F(h->wide.d_rows); F(h->wide.d_colend); F(h->wide.d_in_off);
   F(h->gt.d_rows); F(h->gt.d_data); F(h->gt.d_mr); F(h->gt.d_in_off); F(h->d_tree_ranges);
@@ -339,6 +339,13 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
       return H2_EUNSUPPORTED;
     }
     plan.out = outl[0];
+    // regions of the fragment-ordered copies (made by h2_tune)
+    std::map<FlKey, int64_t> keys;
+    for (const auto* v : {&plan.up, &plan.couple, &plan.down, &plan.dense, &plan.dense2, &plan.couple_loc,
+                          &plan.dense_loc, &plan.dense2_loc, &plan.couple_deep, &plan.couple_rest})
+      for (const Launch& L : *v)
+        if (L.kind == KIND_STREAM) place_fl(h->rt, L.row_begin, L.row_begin + L.row_count, L.arr, &keys, &h->n_fl);
+    place_fl(h->rt, plan.out.row_begin, plan.out.row_begin + plan.out.row_count, plan.out.arr, &keys, &h->n_fl);
   }
   std::vector<int2> tree_ranges;
   h->tree_ok = build_tree_groups(h, P, lay, &tree_ranges);
@@ -608,10 +615,13 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
   if (nvp > 0 && (kcw == kWaveRows || kcw == kWaveTiles) && L.max_rows <= 64) {
     const bool narrow = kcw == kWaveTiles;
     const int rm = L.remapp[lowp ? H2_PREC_FP32 : H2_PREC_FP64];
+    const bool fl = L.flp[lowp ? H2_PREC_FP32 : H2_PREC_FP64] != 0;
     e = lowp ? launch_wave_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm)
+                                       data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm,
+                                       fl ? h->d_fl32 : nullptr)
              : launch_wave_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
-                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm);
+                                        data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm,
+                                        fl ? h->d_fl : nullptr);
   } else if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
@@ -660,6 +670,85 @@ int prepare_f32(h2_op_s* h) {
   HIP_TRY(launch_to_f32(h->d_trans, t32, h->n_trans, nullptr), "FP32 copy");
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize(FP32 copy)");
   h->stats.device_bytes += (int64_t)sizeof(float) * (h->n_lowrank + h->n_trans);
+  return H2_OK;
+}
+
+// The fragment-ordered copies of the op-'N' rows for the wave-row kernels:
+// FP64 of every row, and for FP32 (after prepare_f32) of the low-rank rows.
+int prepare_fl(h2_op_s* h, int prec) {
+  std::lock_guard<std::mutex> lock(h->prep_mu);
+  if (h->n_fl == 0 || !h->mfma_ok) return H2_OK;
+  const Plan& p = h->planN;
+  // one copy: every launch's rows (FP64), or the low-rank ones (FP32); the
+  // handle keeps it only when every relayout ran
+  auto make = [&](void* d, bool fp32) -> hipError_t {
+    hipError_t e = hipSuccess;
+    auto one = [&](const Launch& L) {
+      if (e != hipSuccess || (fp32 && !L.lowrank)) return;  // the dense rows stay FP64
+      if (fp32)
+        e = launch_rows_to_fl<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend,
+                                     L.arr == ARR_TRANS ? h->d_trans32 : h->d_mat32, static_cast<float*>(d), nullptr);
+      else
+        e = launch_rows_to_fl<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend,
+                                      L.arr == ARR_TRANS ? h->d_trans : h->d_mat, static_cast<double*>(d), nullptr);
+    };
+    for (const auto* v : {&p.up, &p.couple, &p.down, &p.dense, &p.dense2, &p.couple_loc, &p.dense_loc,
+                          &p.dense2_loc, &p.couple_deep, &p.couple_rest})
+      for (const Launch& L : *v) one(L);
+    one(p.out);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e;
+  };
+  if (!h->d_fl) {
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d), sizeof(double) * h->n_fl), "hipMalloc(fragment-ordered copy)");
+    const hipError_t e = make(d, false);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(e, "fragment-ordered copy");
+    }
+    h->d_fl = d;
+    h->stats.device_bytes += (int64_t)sizeof(double) * h->n_fl;
+  }
+  if (prec == H2_PREC_FP32 && h->d_mat32 && !h->d_fl32) {
+    float* d = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d), sizeof(float) * h->n_fl), "hipMalloc(fragment-ordered copy)");
+    const hipError_t e = make(d, true);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(e, "fragment-ordered copy");
+    }
+    h->d_fl32 = d;
+    h->stats.device_bytes += (int64_t)sizeof(float) * h->n_fl;
+  }
+  return H2_OK;
+}
+
+// Frees a fragment-ordered copy that no tuned launch reads (the FP64 copy
+// serves every precision's dense rows through their FP64 entry).
+int drop_unused_fl(h2_op_s* h) {
+  std::lock_guard<std::mutex> lock(h->prep_mu);
+  bool use64 = false, use32 = false;
+  auto look = [&](const Launch& L) {
+    auto reads = [&](int p) { return (L.kcp[p] == kWaveRows || L.kcp[p] == kWaveTiles) && L.flp[p] != 0; };
+    use64 = use64 || reads(H2_PREC_FP64);
+    use32 = use32 || (L.lowrank && reads(H2_PREC_FP32));
+  };
+  const Plan& p = h->planN;
+  for (const auto* v : {&p.up, &p.couple, &p.down, &p.dense, &p.dense2, &p.couple_loc, &p.dense_loc,
+                        &p.dense2_loc, &p.couple_deep, &p.couple_rest})
+    for (const Launch& L : *v) look(L);
+  look(p.out);
+  if (!use64 && h->d_fl) {
+    HIP_TRY(hipFree(h->d_fl), "hipFree(fragment-ordered copy)");
+    h->d_fl = nullptr;
+    h->stats.device_bytes -= (int64_t)sizeof(double) * h->n_fl;
+  }
+  if (!use32 && h->d_fl32) {
+    HIP_TRY(hipFree(h->d_fl32), "hipFree(fragment-ordered copy)");
+    h->d_fl32 = nullptr;
+    h->stats.device_bytes -= (int64_t)sizeof(float) * h->n_fl;
+  }
   return H2_OK;
 }
 
@@ -1155,6 +1244,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   if ((rc = h2_prepare(h, prec)) != H2_OK) return rc;
   if ((rc = ensure_workspace(h, prec == H2_PREC_BF16 ? kPassVectorsMfma : nv)) != H2_OK) return rc;
   if (!h->mfma_ok) return H2_OK;
+  if (prec != H2_PREC_BF16 && (rc = prepare_fl(h, prec)) != H2_OK) return rc;
   const int nvp = (int)std::min<int64_t>((nv + 15) / 16 * 16, kPassVectorsMfma);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Workspace& w = h->ws;
@@ -1183,16 +1273,20 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     const int kcs[13] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8, kWaveRows, kWaveTiles};
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
-    int best_kc = L.kcp[pi], best_remap = L.remapp[pi];
+    int best_kc = L.kcp[pi], best_remap = L.remapp[pi], best_fl = L.flp[pi];
     int64_t best_grid = L.gridp[pi];
+    // the wave-row kernels also without the fragment-ordered copy
+    const bool has_fl = pi == H2_PREC_FP32 ? h->d_fl32 != nullptr : h->d_fl != nullptr;
     for (int kc : kcs) {
       if (pi == H2_PREC_BF16 && kc != 64) continue;  // the BF16 kernel has one chunk width
       if (kc >= 0 && kc <= 8 && nvp != 64) continue;
       if (kc >= 1 && kc <= 8 && L.max_rows > 64) continue;
       if ((kc == kWaveRows || kc == kWaveTiles) && L.max_rows > 64) continue;
       if (kc == kWaveTiles && nvp != 32 && nvp != 64) continue;
+      const bool wave = kc == kWaveRows || kc == kWaveTiles;
       for (int64_t g : grids)
-        for (int remap = 0; remap < 2; ++remap) {
+        for (int cand = 0; cand < (wave && has_fl ? 4 : 2); ++cand) {
+          const int remap = cand & 1, fl = wave && has_fl ? cand >> 1 : 1;
           if (g != 0 && g >= L.row_count) continue;
           // the dense rows run beside the sweeps: a persistent grid would hold
           // every CU slot and starve them, so they keep one workgroup per row
@@ -1201,6 +1295,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
           T.kcp[pi] = kc;
           T.gridp[pi] = g;
           T.remapp[pi] = remap;
+          T.flp[pi] = fl;
           float tsum = 0.0f;
           for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
@@ -1218,12 +1313,14 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
             best_kc = kc;
             best_grid = g;
             best_remap = remap;
+            best_fl = fl;
           }
         }
     }
     L.kcp[pi] = best_kc;
     L.gridp[pi] = best_grid;
     L.remapp[pi] = best_remap;
+    L.flp[pi] = best_fl;
     L.tuned_ms[pi] = best / 2;
     if (tbest) *tbest = best;
     return H2_OK;
@@ -1313,6 +1410,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc == H2_OK) rc = drop_unused_fl(h);
   return rc;
 }
 
@@ -1337,16 +1435,19 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
       L.kcp[prec] = kc;
       L.gridp[prec] = grid;
       L.remapp[prec] = xcd ? 1 : 0;
+      L.flp[prec] = 1;
     }
   P.out.kcp[prec] = kc;
   P.out.gridp[prec] = grid;
   P.out.remapp[prec] = xcd ? 1 : 0;
+  P.out.flp[prec] = 1;
   if (prec == H2_PREC_FP64 || kc != 0)  // the dense rows are always FP64
     for (auto* v : {&P.dense, &P.dense2, &P.dense_loc, &P.dense2_loc})
       for (Launch& L : *v) {
         L.kcp[H2_PREC_FP64] = prec == H2_PREC_BF16 ? 64 : kc;
         L.gridp[H2_PREC_FP64] = grid;
         L.remapp[H2_PREC_FP64] = xcd ? 1 : 0;
+        L.flp[H2_PREC_FP64] = 1;
       }
   h->couple_mode[prec] = tree_order != 0 ? 1 : 0;
   h->dense_mode[prec] = tree_order != 0 ? 1 : 0;
@@ -1392,6 +1493,28 @@ int h2_set_sweeps(h2_handle h, int prec, int fused) {
   return H2_OK;
 }
 
+int h2_set_fragment_order(h2_handle h, int prec, int enable) {
+  if (!h) { set_error("null handle"); return H2_EINVAL; }
+  if (prec != H2_PREC_FP64 && prec != H2_PREC_FP32) {
+    set_error("the fragment-ordered copies exist for FP64 and FP32");
+    return H2_EINVAL;
+  }
+  DeviceGuard guard(h->device);
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  drop_graphs(h);
+  int rc;
+  if (enable) {
+    if ((rc = h2_prepare(h, prec)) != H2_OK || (rc = prepare_fl(h, prec)) != H2_OK) return rc;
+  }
+  Plan& P = h->planN;
+  for (auto* v : {&P.up, &P.couple, &P.down, &P.couple_loc, &P.couple_deep, &P.couple_rest})
+    for (Launch& L : *v) L.flp[prec] = enable ? 1 : 0;
+  P.out.flp[prec] = enable ? 1 : 0;
+  for (auto* v : {&P.dense, &P.dense2, &P.dense_loc, &P.dense2_loc})  // always FP64
+    for (Launch& L : *v) L.flp[H2_PREC_FP64] = enable ? 1 : 0;
+  return enable ? H2_OK : drop_unused_fl(h);
+}
+
 int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
   if (!h || !needed) { set_error("null handle or size output"); return H2_EINVAL; }
   std::string t;
@@ -1409,8 +1532,8 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
                     L.kind);
       t += line;
       for (int p = 0; p < 3; ++p) {
-        std::snprintf(line, sizeof line, " | %s kc=%d grid=%lld xcd=%d %.3fms", pn[p], L.kcp[p],
-                      (long long)L.gridp[p], L.remapp[p], L.tuned_ms[p]);
+        std::snprintf(line, sizeof line, " | %s kc=%d grid=%lld xcd=%d fl=%d %.3fms", pn[p], L.kcp[p],
+                      (long long)L.gridp[p], L.remapp[p], L.flp[p], L.tuned_ms[p]);
         t += line;
       }
       t += "\n";

@@ -15,6 +15,8 @@
 // of the groups follow each other, interleaved level by level.
 #include <algorithm>
 #include <array>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <string>
@@ -212,10 +214,10 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
         }
     for (int64_t h = 0; h <= b->maxq; ++h)
       if (add_phase(b, up[h], ARR_TRANS, MODE_STORE, false, true, G.up)) G.up_level.push_back(h);
-    add_phase(b, couple, ARR_MAT, MODE_STORE, true, true, G.couple);
+    add_phase(b, couple, ARR_MAT, MODE_STORE, false, true, G.couple);
     for (int64_t d = 0; d < b->maxq; ++d)
       if (add_phase(b, down[d], ARR_MAT, MODE_ACCUM, false, true, G.down)) G.down_level.push_back(d);
-    add_phase(b, dense, ARR_MAT, MODE_STORE, true, false, G.dense);
+    add_phase(b, dense, ARR_MAT, MODE_STORE, false, false, G.dense);
     add_phase(b, outr, ARR_MAT, MODE_ACCUM, false, true, G.out);
   }
 
@@ -250,6 +252,7 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   if ((rc = up_tab(b->rt.rows, &b->rt.d_rows)) || (rc = up_tab(b->rt.colend, &b->rt.d_colend)) ||
       (rc = up_tab(b->rt.in_off, &b->rt.d_in_off)))
     return rc;
+
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     Group& G = b->groups[gi];
     // permutation tiles: kPermTile original rows of one operator each
@@ -533,10 +536,11 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
         for (int kc : kcs)
           for (int64_t gsz : grids)
             for (int remap = 0; remap < 2; ++remap) {
+            const bool wave = kc == kWaveRows || kc == kWaveTiles;
             if (gsz != 0 && gsz >= L.row_count) continue;
-            if ((kc == kWaveRows || kc == kWaveTiles) && L.max_rows > 64) continue;
+            if (wave && L.max_rows > 64) continue;
             if (kc == kWaveTiles && G.nvp != 32 && G.nvp != 64) continue;
-            if (remap && kc != kWaveRows && kc != kWaveTiles) continue;  // XCD ranges: wave-row kernels only
+            if (remap && !wave) continue;  // XCD ranges: wave-row kernels only
             Launch T = L;
             T.kc = kc;
             T.grid = gsz;
@@ -561,6 +565,7 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
         L.kc = best_kc;
         L.grid = best_grid;
         L.remapp[0] = best_remap;
+        L.tuned_ms[0] = best / 2;
       }
   // the dense rows' schedule, on whole launch sequences (a warm-up, then two
   // timed runs each)
@@ -605,6 +610,37 @@ int h2_batch_info(h2_batch b, int64_t* count, int64_t* total_n, double* flops_pe
   if (total_n) *total_n = b->total_n;
   if (flops_per_vector) *flops_per_vector = b->flops_per_vector;
   if (launches) *launches = launch_count(b);
+  return H2_OK;
+}
+
+int h2_batch_plan_info(h2_batch b, char* buf, size_t cap, size_t* needed) {
+  if (!b || !needed) { set_error("null batch or size output"); return H2_EINVAL; }
+  std::string t;
+  char line[256];
+  std::snprintf(line, sizeof line, "schedule %s (tuned calls %.3f / %.3f / %.3f ms)\n",
+                b->par ? "groups side by side" : b->sched == 1 ? "dense after the upsweep" : "dense from the start",
+                b->sched_ms[0], b->sched_ms[1], b->sched_ms[2]);
+  t += line;
+  for (const Group& G : b->groups) {
+    std::snprintf(line, sizeof line, "group nvp=%d\n", G.nvp);
+    t += line;
+    const char* names[5] = {"up", "couple", "down", "dense", "out"};
+    int k = 0;
+    for (const auto* v : {&G.up, &G.couple, &G.down, &G.dense, &G.out}) {
+      for (const Launch& L : *v) {
+        std::snprintf(line, sizeof line, "%s rows=%lld max_rows=%d kc=%d grid=%lld xcd=%d %.3fms\n", names[k],
+                      (long long)L.row_count, L.max_rows, L.kc, (long long)L.grid, L.remapp[0], L.tuned_ms[0]);
+        t += line;
+      }
+      ++k;
+    }
+  }
+  *needed = t.size() + 1;
+  if (buf && cap > 0) {
+    const size_t c = std::min(cap - 1, t.size());
+    std::memcpy(buf, t.data(), c);
+    buf[c] = 0;
+  }
   return H2_OK;
 }
 

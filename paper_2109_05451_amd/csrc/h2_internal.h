@@ -7,6 +7,7 @@
 
 #include <array>
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -64,6 +65,7 @@ struct RowDesc {
   int32_t pad;
   int64_t out_ld;    // output stride between vectors
   int64_t in_ld;     // input stride between vectors
+  int64_t fl_off;    // element offset of the row's fragment-ordered copy (wave-row kernels), even
 };
 
 // Row schedules of the streaming kernel: per block, the cumulative end
@@ -112,6 +114,7 @@ struct Launch {
   int kcp[3] = {64, 64, 64};
   int64_t gridp[3] = {0, 0, 0};
   int remapp[3] = {0, 0, 0};  // XCD-aware row ranges
+  int flp[3] = {1, 1, 1};     // wave-row kernels: read the fragment-ordered copy when there is one
   float tuned_ms[3] = {0, 0, 0};  // time of the chosen setting when tuned (two runs)
 };
 
@@ -240,6 +243,17 @@ void build_transposed(const uint8_t* buf, const OpLayout& L, double* tr);
 void emit_rows_N(const OpLayout& L, const RowBases& B, RowsN* R);
 void append_row(RowTables& t, const RowSpec& r);
 int64_t row_work(const RowSpec& r);
+// Places the fragment-ordered copy of rows [begin, end) of t: rows with the
+// same matrix (array, offset and shape) share one region; regions start at
+// even offsets.  *n_fl grows by the elements placed.  `keys` carries the
+// placed regions between calls.
+struct FlKey {
+  int arr;
+  int64_t data_off;
+  int32_t nrows, ncols;
+  bool operator<(const FlKey& o) const;
+};
+void place_fl(RowTables& t, int64_t begin, int64_t end, int arr, std::map<FlKey, int64_t>* keys, int64_t* n_fl);
 
 // Per-product scratch: X~ and the dense partial (n x cap), x^ and y^
 // (H x cap) in doubles; the streaming path uses them column-major with up
@@ -301,6 +315,12 @@ struct h2_op_s {
   float* d_trans32 = nullptr;
   void* d_mat16 = nullptr;    // BF16 copies of the op-'N' low-rank rows, row-major per row
   void* d_trans16 = nullptr;
+  // fragment-ordered copies of the op-'N' rows (FP64 every row, FP32 the
+  // low-rank rows) at the rows' fl_off, read by the wave-row kernels; made by
+  // h2_tune on the multi-vector path
+  int64_t n_fl = 0;
+  double* d_fl = nullptr;
+  float* d_fl32 = nullptr;
   std::mutex prep_mu;         // guards the lazy creation of the FP32 and BF16 copies
   int32_t* d_perm = nullptr;
   int32_t* d_pinv = nullptr;  // original index -> tree position
@@ -404,10 +424,16 @@ hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double al
 // the tuner), or one wave per 16-vector tile of a row (kWaveTiles); grid =
 // workgroups (0: enough for every row at once); remap: XCD-aware row ranges
 constexpr int kWaveRows = 9, kWaveTiles = 10;
+// fl: the fragment-ordered copy of the rows' matrices (rows' fl_off), read
+// instead of `data` when not null; the results are bitwise the same
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid, bool narrow = false, int remap = 0);
+                            hipStream_t s, int64_t grid, bool narrow = false, int remap = 0, const T* fl = nullptr);
+// dst[R.fl_off ...] = the fragment-ordered copy of every row's matrix at src[R.data_off ...]
+template <typename T>
+hipError_t launch_rows_to_fl(const RowDesc* rows, int64_t nrows, const int32_t* colend, const T* src, T* dst,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
                        const int32_t* colend, const int64_t* in_off, const T* data, double* const bufs[4], int nvp,

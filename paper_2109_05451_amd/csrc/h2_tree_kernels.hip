@@ -57,7 +57,13 @@ __device__ __forceinline__ double* pick(int i, double* b0, double* b1, double* b
 // over the row's blocks; its column grows by four per step.
 // The row's block table is colend[b0 .. b0 + nb), in_off[b0 .. b0 + nb):
 // the global tables (b0 = R.blk_begin) or a wave's copy in LDS (b0 = 0).
-template <typename T, int NT, int NTW, int MT>
+//
+// FL: the matrix is read from the row's fragment-ordered copy at
+// data + R.fl_off instead (see k_rows_to_fl): the same values reach the same
+// MFMA operands, so the result is bitwise the same, but every load of a
+// wave reads whole 128-byte lines (two four-column steps per lane, 16 bytes
+// for FP64) instead of 16-row pieces of columns that straddle lines.
+template <typename T, int NT, int NTW, int MT, bool FL = false>
 __device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* colend, const int64_t* in_off, int b0,
                                          const T* __restrict__ data, const double* in, double* out, int mode,
                                          int lane, int vt0) {
@@ -77,7 +83,14 @@ __device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* colend
   int b = b0, bstart = 0;
   int bend = nb > 0 ? colend[b] : 0;
   int64_t boff = nb > 0 ? in_off[b] : 0;
-  const T* M = data + R.data_off;
+  // fragment order: npair full pairs of four-column steps, each 8m values
+  // (full 16-row tiles: 128 values in lane order, two per lane; the last
+  // m % 16 rows: 8 (m % 16) values, two per active lane), then the last
+  // ncols % 8 columns column-major
+  const int npair = FL ? ncols >> 3 : 0;
+  const int nfull = m >> 4, rem = m & 15;
+  const T* M = data + (FL ? R.fl_off : R.data_off);
+  const T* Mt = M + (int64_t)8 * m * npair;
   // four-column steps loaded per iteration: four, or two when the
   // accumulators are many (keeps two waves per SIMD at 64 rows x 64 vectors)
   constexpr int U = MT * NTW > 8 ? 2 : 4;
@@ -98,10 +111,45 @@ __device__ __forceinline__ void wave_row(const RowDesc& R, const int32_t* colend
       const double* src = in + (boff + (col - bstart)) * NVP + 16 * vt0 + arow;
 #pragma unroll
       for (int j = 0; j < NTW; ++j) bf[u][j] = ok ? (T)src[16 * j] : (T)0;
+      if (!FL) {
 #pragma unroll
-      for (int ti = 0; ti < MT; ++ti) {
-        const int r = 16 * ti + arow;
-        a[u][ti] = (ok && ti < mt && r < m) ? __builtin_nontemporal_load(M + r + (int64_t)m * col) : (T)0;
+        for (int ti = 0; ti < MT; ++ti) {
+          const int r = 16 * ti + arow;
+          a[u][ti] = (ok && ti < mt && r < m) ? __builtin_nontemporal_load(M + r + (int64_t)m * col) : (T)0;
+        }
+      }
+    }
+    if (FL) {
+      typedef T t2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int u2 = 0; u2 < U / 2; ++u2) {
+        const int p = (c0 >> 3) + u2;  // wave-uniform
+        if (p < npair) {
+          const T* P = M + (int64_t)8 * m * p;
+#pragma unroll
+          for (int ti = 0; ti < MT; ++ti) {
+            t2 v = t2{(T)0, (T)0};
+            if (ti < nfull)
+              v = __builtin_nontemporal_load(reinterpret_cast<const t2*>(P + 128 * ti + 2 * lane));
+            else if (ti == nfull && arow < rem)
+              v = __builtin_nontemporal_load(reinterpret_cast<const t2*>(P + 128 * nfull + 2 * (akk * rem + arow)));
+            a[2 * u2][ti] = v[0];
+            a[2 * u2 + 1][ti] = v[1];
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int col = c0 + 8 * u2 + 4 * h + akk;
+            const bool ok = col < ncols;
+#pragma unroll
+            for (int ti = 0; ti < MT; ++ti) {
+              const int r = 16 * ti + arow;
+              a[2 * u2 + h][ti] = (ok && ti < mt && r < m)
+                                      ? __builtin_nontemporal_load(Mt + r + (int64_t)m * (col - 8 * npair))
+                                      : (T)0;
+            }
+          }
+        }
       }
     }
 #pragma unroll
@@ -168,7 +216,7 @@ __global__ __launch_bounds__(kT) void k_tree(const int2* __restrict__ ranges, Tr
 // wave copies its row's block table into its own LDS region first, so the
 // column cursor (one step per block, dozens of blocks in a coupling or dense
 // row) reads LDS instead of waiting on dependent global loads.
-template <typename T, int NT, int NTW, int MT>
+template <typename T, int NT, int NTW, int MT, bool FL>
 __global__ __launch_bounds__(kT) void k_wave_rows(const RowDesc* __restrict__ rows, int64_t nrows,
                                                   const int32_t* __restrict__ colend,
                                                   const int64_t* __restrict__ in_off, const T* __restrict__ data,
@@ -200,7 +248,50 @@ __global__ __launch_bounds__(kT) void k_wave_rows(const RowDesc* __restrict__ ro
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    wave_row<T, NT, NTW, MT>(R, s_end[wave], s_in[wave], 0, data, in, out, mode, lane, vt0);
+    wave_row<T, NT, NTW, MT, FL>(R, s_end[wave], s_in[wave], 0, data, in, out, mode, lane, vt0);
+  }
+}
+
+// The fragment-ordered copy of each row (one workgroup per row,
+// grid-stride): dst[R.fl_off + e], e < m * ncols, from the column-major
+// src[R.data_off + r + m * c].  For e < 8 m npair (npair = ncols / 8): pair
+// p = e / 8m of four-column steps; within it, full row tile t, lane l
+// (row 16 t + l % 16, step column l / 16) and step u at 128 t + 2 l + u,
+// then the last rem = m % 16 rows, lane i + 16 k (i < rem) at
+// 128 (m / 16) + 2 (k rem + i) + u; the column is 8 p + 4 u + k.  The last
+// ncols % 8 columns follow column-major.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_to_fl(const RowDesc* __restrict__ rows, int64_t nrows,
+                                                    const int32_t* __restrict__ colend, const T* __restrict__ src,
+                                                    T* __restrict__ dst) {
+  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+    const RowDesc R = rows[ri];
+    const int m = R.nrows, nb = R.blk_end - R.blk_begin;
+    const int ncols = nb > 0 ? colend[R.blk_end - 1] : 0;
+    const int64_t npair = ncols >> 3, body = (int64_t)8 * m * npair, total = (int64_t)m * ncols;
+    const int nfull = m >> 4, rem = m & 15;
+    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+      int64_t r, c;
+      if (e < body) {
+        const int64_t p = e / (8 * m);
+        const int x = (int)(e - p * 8 * m);
+        int u, k, i;
+        if (x < 128 * nfull) {
+          const int t = x >> 7, y = x & 127, l = y >> 1;
+          u = y & 1; k = l >> 4; i = 16 * t + (l & 15);
+        } else {
+          const int y = x - 128 * nfull, l = y >> 1;
+          u = y & 1; k = l / rem; i = 16 * nfull + l % rem;
+        }
+        r = i;
+        c = 8 * p + 4 * u + k;
+      } else {
+        const int64_t t = e - body;
+        r = t % m;
+        c = 8 * npair + t / m;
+      }
+      dst[R.fl_off + e] = src[R.data_off + r + (int64_t)m * c];
+    }
   }
 }
 
@@ -279,26 +370,44 @@ inline int64_t wave_grid(int64_t nrows, int rpw, int64_t grid, int remap) {
 }
 
 template <typename T>
+hipError_t launch_rows_to_fl(const RowDesc* rows, int64_t nrows, const int32_t* colend, const T* src, T* dst,
+                             hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_to_fl<T>, dim3((unsigned)std::min<int64_t>(nrows, 65536)), dim3(256), 0, s, rows, nrows,
+                     colend, src, dst);
+  return hipGetLastError();
+}
+template hipError_t launch_rows_to_fl<double>(const RowDesc*, int64_t, const int32_t*, const double*, double*,
+                                              hipStream_t);
+template hipError_t launch_rows_to_fl<float>(const RowDesc*, int64_t, const int32_t*, const float*, float*,
+                                             hipStream_t);
+
+template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid, bool narrow, int remap) {
+                            hipStream_t s, int64_t grid, bool narrow, int remap, const T* fl) {
   if (nrows == 0) return hipSuccess;
   if (max_rows > 64) return hipErrorInvalidValue;
   // narrow: a wave per 16-vector tile (NT waves per row, more waves resident); else a wave per row, or
   // two when one wave's accumulators would leave a single wave per SIMD
+#define H2_WR_K(NT, NTW, MT, G)                                                                          \
+  do {                                                                                                   \
+    if (fl)                                                                                              \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, true>), G, dim3(kT), 0, s, rows, nrows, colend, in_off, \
+                         fl, in, out, mode, remap);                                                      \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, false>), G, dim3(kT), 0, s, rows, nrows, colend, in_off, \
+                         data, in, out, mode, remap);                                                    \
+  } while (0)
 #define H2_WR(NT, MT)                                                                                    \
   do {                                                                                                   \
     if (narrow && (NT == 2 || NT == 4)) {                                                                \
       constexpr int RPWN = 4 / NT;                                                                       \
-      const dim3 gn((unsigned)wave_grid(nrows, RPWN, grid, remap)), bn(kT);                              \
-      hipLaunchKernelGGL((k_wave_rows<T, NT, 1, MT>), gn, bn, 0, s, rows, nrows, colend, in_off, data, in, out, \
-                         mode, remap);                                                                   \
+      H2_WR_K(NT, 1, MT, dim3((unsigned)wave_grid(nrows, RPWN, grid, remap)));                           \
       break;                                                                                             \
     }                                                                                                    \
     constexpr int NTW = (MT * NT > 8 && NT % 2 == 0) ? NT / 2 : NT, RPW = 4 / (NT / NTW);               \
-    const dim3 g((unsigned)wave_grid(nrows, RPW, grid, remap)), b(kT);                                   \
-    hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT>), g, b, 0, s, rows, nrows, colend, in_off, data, in, out, \
-                       mode, remap);                                                                     \
+    H2_WR_K(NT, NTW, MT, dim3((unsigned)wave_grid(nrows, RPW, grid, remap)));                           \
   } while (0)
 #define H2_WR_NT(NT)                          \
   do {                                        \
@@ -316,12 +425,15 @@ hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* c
   }
 #undef H2_WR_NT
 #undef H2_WR
+#undef H2_WR_K
   return hipGetLastError();
 }
 template hipError_t launch_wave_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
-                                             const double*, double*, int, int, int, hipStream_t, int64_t, bool, int);
+                                             const double*, double*, int, int, int, hipStream_t, int64_t, bool, int,
+                                             const double*);
 template hipError_t launch_wave_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
-                                            const double*, double*, int, int, int, hipStream_t, int64_t, bool, int);
+                                            const double*, double*, int, int, int, hipStream_t, int64_t, bool, int,
+                                            const float*);
 
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,
