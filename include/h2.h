@@ -220,12 +220,14 @@ int h2_reserve(h2_handle h, int64_t nv_max);
  * then the fused sweeps are timed against the tuned per-level sweeps and the
  * faster form is kept (h2_set_sweeps), and the four schedules of
  * h2_set_schedule are timed on whole products (zeroed input) and the
- * fastest is kept.
+ * fastest is kept (a later schedule in the list only when it is at least 1%
+ * faster than the best before it, so that timing noise does not decide).
  * Results do not depend on the choice: every candidate sums each output in
  * the same order, so they are bitwise identical.  For nv <= 4 outside BF16
  * (the streaming path) it times the four schedules of h2_set_schedule on
- * whole products and keeps the fastest.  Synchronous; must not run concurrently with other calls on the
- * handle (it uses the handle's workspace).
+ * whole products and keeps the fastest (by the same 1% rule).  Synchronous;
+ * must not run concurrently with other calls on the handle (it uses the
+ * handle's workspace).
  * Errors: H2_EINVAL (null handle, nv < 0, unknown precision), H2_ENOMEM,
  * H2_EHIP. */
 int h2_tune(h2_handle h, int64_t nv, int prec, void* stream);
@@ -420,7 +422,8 @@ int h2_batch_gemv(h2_batch b, const h2_batch_item* items, void* stream);
  * whole calls with the dense rows on the second stream from the start
  * (beside the upsweep) or from the end of the upsweep (beside the coupling
  * launches), and with each vector-width group's sweeps and coupling rows on
- * a stream of its own, and keep the fastest.  Results do not depend on the
+ * a stream of its own, and keep the fastest (a later form only when at
+ * least 1% faster than the best before it).  Results do not depend on the
  * choices.
  * Synchronous; the workspace content afterwards is unspecified. */
 int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream);

@@ -1090,6 +1090,11 @@ namespace {
 // Streaming products (nv <= kPassVectors): the four schedules of
 // h2_set_schedule timed on whole products (a warm-up, then three runs each)
 // on zeroed buffers; the fastest is kept.
+// A schedule later in the list replaces the best so far only when it is at
+// least 1% faster: schedules differ by a few per cent at most, and a choice
+// made on timing noise would move the launches' overlap from run to run.
+constexpr float kScheduleGain = 0.99f;
+
 int tune_stream_schedule(h2_op_s* h, int64_t nv, int prec, void* stream) {
   if (nv == 0) return H2_OK;
   DeviceGuard guard(h->device);
@@ -1138,7 +1143,7 @@ int tune_stream_schedule(h2_op_s* h, int64_t nv, int prec, void* stream) {
       if (rep > 0) t += ms;
     }
     h->sched1_ms[prec][sc] = t / 3;
-    if (t < best) {
+    if (t < best * kScheduleGain) {
       best = t;
       best_s = sc;
     }
@@ -1397,7 +1402,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
           if (rep > 0) t += ms;
         }
         h->sched_ms[prec][sc] = t / 3;
-        if (t < best) {
+        if (t < best * kScheduleGain) {
           best = t;
           best_s = sc;
         }

@@ -586,7 +586,7 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
   }
   int best = 0;
   for (int sc = 1; sc < 3; ++sc)
-    if (b->sched_ms[sc] < b->sched_ms[best]) best = sc;
+    if (b->sched_ms[sc] < 0.99f * b->sched_ms[best]) best = sc;  // a later form only when 1% faster
   b->sched = best == 1 ? 1 : 0;
   b->par = best == 2;
   (void)hipEventDestroy(e0);
