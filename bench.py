@@ -35,12 +35,13 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, datasheet (no sparsity)
 KERNEL_SOURCES = ("h2_kernels.hip", "h2_tree_kernels.hip")
 
 
-def kernel_source_md5() -> str:
-    """md5 of the kernel sources (in KERNEL_SOURCES order) that the profile
-    summaries record; None if one is missing."""
+def kernel_source_md5(files=KERNEL_SOURCES) -> str:
+    """md5 of the kernel sources (concatenated in the order given; by default
+    KERNEL_SOURCES) that the profile summaries record; None if one is
+    missing."""
     import hashlib
     m = hashlib.md5()
-    for f in KERNEL_SOURCES:
+    for f in files:
         path = os.path.join(ROOT, "paper_2109_05451_amd", "csrc", f)
         if not os.path.exists(path):
             return None
@@ -59,9 +60,14 @@ def measured_traffic(config: str, nv: int, phase: str, precision: str = "fp64"):
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m5 = re.search(r"kernel_source_md5: `([0-9a-f]+)`", text)
+    # the summary names the source files of the priced kernel it hashed
+    # ("(of: a.hip, b.hip)"); without a list, every kernel source
+    m5 = re.search(r"kernel_source_md5: `([0-9a-f]+)`(?: \(of: ([^)]*)\))?", text)
     tb = re.search(r"traffic_bytes_per_launch \(" + phase + r" rows\): ([0-9.eE+]+)", text)
-    if not m5 or not tb or m5.group(1) != kernel_source_md5():
+    if not m5 or not tb:
+        return None
+    files = tuple(f.strip() for f in m5.group(2).split(",")) if m5.group(2) else KERNEL_SOURCES
+    if m5.group(1) != kernel_source_md5(files):
         return None
     return float(tb.group(1))
 
@@ -142,7 +148,7 @@ def tuned_coupling_ms(info: str, precision: str):
         ("couple_tree",) if tree else ("couple",))
     total = 0.0
     for nm in names:
-        m = re.search(r"^" + nm + r" rows=.*?\| " + precision + r" kc=\S+ grid=\S+ xcd=\S+ (?:fl=\S+ )?([0-9.]+)ms",
+        m = re.search(r"^" + nm + r" rows=.*?\| " + precision + r" kc=\S+ grid=\S+ xcd=\S+ (?:fl=\S+ )?(?:occ=\S+ )?([0-9.]+)ms",
                       info, re.M)
         if not m or float(m.group(1)) <= 0.0:
             return None

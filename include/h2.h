@@ -286,7 +286,9 @@ int h2_ranks(h2_handle h, int64_t* krow, int64_t* kcol, int64_t cap);
  * passes of 64 vectors, 1-8 rows of at most 64 outputs; other launches use
  * 64 columns), 9 for one wave per row with no LDS staging (rows of at most
  * 64 outputs, any pass width), 10 the same with one wave per 16-vector tile
- * (passes of 32 or 64 vectors); grid = workgroups (0 = one per
+ * (passes of 32 or 64 vectors), 11 and 12 the forms of 9 and 10 compiled for
+ * five waves per SIMD (where one wave holds one 16-vector tile of rows of at
+ * most 48 outputs; else the forms of 9 and 10); grid = workgroups (0 = one per
  * row); xcd != 0 for XCD-aware row ranges; tree_order != 0 for tree-ordered
  * coupling and dense rows.  Results do not change (same summation order).  For
  * reproducible timing and for tests.  Errors: H2_EINVAL. */

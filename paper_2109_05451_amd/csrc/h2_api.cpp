@@ -616,12 +616,13 @@ int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Ep
     const bool narrow = kcw == kWaveTiles;
     const int rm = L.remapp[lowp ? H2_PREC_FP32 : H2_PREC_FP64];
     const bool fl = L.flp[lowp ? H2_PREC_FP32 : H2_PREC_FP64] != 0;
+    const int occ = L.occp[lowp ? H2_PREC_FP32 : H2_PREC_FP64];
     e = lowp ? launch_wave_rows<float>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
                                        data32, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm,
-                                       fl ? h->d_fl32 : nullptr)
+                                       fl ? h->d_fl32 : nullptr, occ)
              : launch_wave_rows<double>(h->rt.d_rows + L.row_begin, L.row_count, h->rt.d_colend, h->rt.d_in_off,
                                         data, bufs[L.in], out, nvp, mode, L.max_rows, s, grid_of, narrow, rm,
-                                        fl ? h->d_fl : nullptr);
+                                        fl ? h->d_fl : nullptr, occ);
   } else if (nvp > 0) {
     const int pi = lowp ? H2_PREC_FP32 : H2_PREC_FP64;
     const float* in32 = lowp && x32 && nvp == kPassVectorsMfma && L.in == BUF_XH ? w.xh32 : nullptr;
@@ -1278,7 +1279,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     const int kcs[13] = {32, 64, 0, 1, 2, 3, 4, 5, 6, 7, 8, kWaveRows, kWaveTiles};
     const int64_t grids[4] = {0, 1024, 2048, 4096};
     float best = 1e30f;
-    int best_kc = L.kcp[pi], best_remap = L.remapp[pi], best_fl = L.flp[pi];
+    int best_kc = L.kcp[pi], best_remap = L.remapp[pi], best_fl = L.flp[pi], best_occ = L.occp[pi];
     int64_t best_grid = L.gridp[pi];
     // the wave-row kernels also without the fragment-ordered copy
     const bool has_fl = pi == H2_PREC_FP32 ? h->d_fl32 != nullptr : h->d_fl != nullptr;
@@ -1290,8 +1291,11 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
       if (kc == kWaveTiles && nvp != 32 && nvp != 64) continue;
       const bool wave = kc == kWaveRows || kc == kWaveTiles;
       for (int64_t g : grids)
-        for (int cand = 0; cand < (wave && has_fl ? 4 : 2); ++cand) {
-          const int remap = cand & 1, fl = wave && has_fl ? cand >> 1 : 1;
+        for (int cand = 0; cand < (wave ? 8 : 2); ++cand) {
+          // wave-row forms: also without the copy, and the five-waves-per-SIMD form
+          const int remap = cand & 1, fl = wave && has_fl ? (cand >> 1) & 1 : 1, occ = cand >> 2 ? 5 : 0;
+          if (wave && !has_fl && (cand >> 1) & 1) continue;
+          if (occ && !wave_occ5(nvp, L.max_rows, kc == kWaveTiles)) continue;
           if (g != 0 && g >= L.row_count) continue;
           // the dense rows run beside the sweeps: a persistent grid would hold
           // every CU slot and starve them, so they keep one workgroup per row
@@ -1301,6 +1305,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
           T.gridp[pi] = g;
           T.remapp[pi] = remap;
           T.flp[pi] = fl;
+          T.occp[pi] = occ;
           float tsum = 0.0f;
           for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipEventRecord(e0, s), "hipEventRecord");
@@ -1319,6 +1324,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
             best_grid = g;
             best_remap = remap;
             best_fl = fl;
+            best_occ = occ;
           }
         }
     }
@@ -1326,6 +1332,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
     L.gridp[pi] = best_grid;
     L.remapp[pi] = best_remap;
     L.flp[pi] = best_fl;
+    L.occp[pi] = best_occ;
     L.tuned_ms[pi] = best / 2;
     if (tbest) *tbest = best;
     return H2_OK;
@@ -1425,10 +1432,13 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
     set_error("unknown precision");
     return H2_EINVAL;
   }
-  if (!(kc >= 0 && kc <= kWaveTiles) && kc != 32 && kc != 64) {
-    set_error("kc must be 0-10, 32 or 64");
+  if (!(kc >= 0 && kc <= kWaveTiles + 2) && kc != 32 && kc != 64) {
+    set_error("kc must be 0-12, 32 or 64");
     return H2_EINVAL;
   }
+  // 11, 12: the wave-row forms compiled for five waves per SIMD
+  const int occ = kc == kWaveTiles + 1 || kc == kWaveTiles + 2 ? 5 : 0;
+  if (occ) kc -= 2;
   if (prec == H2_PREC_BF16 && kc != 64) { set_error("the BF16 kernel has kc 64 only"); return H2_EINVAL; }
   if (grid < 0) { set_error("grid < 0"); return H2_EINVAL; }
   DeviceGuard guard(h->device);
@@ -1441,11 +1451,13 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
       L.gridp[prec] = grid;
       L.remapp[prec] = xcd ? 1 : 0;
       L.flp[prec] = 1;
+      L.occp[prec] = occ;
     }
   P.out.kcp[prec] = kc;
   P.out.gridp[prec] = grid;
   P.out.remapp[prec] = xcd ? 1 : 0;
   P.out.flp[prec] = 1;
+  P.out.occp[prec] = occ;
   if (prec == H2_PREC_FP64 || kc != 0)  // the dense rows are always FP64
     for (auto* v : {&P.dense, &P.dense2, &P.dense_loc, &P.dense2_loc})
       for (Launch& L : *v) {
@@ -1453,6 +1465,7 @@ int h2_tune_set(h2_handle h, int prec, int kc, int64_t grid, int xcd, int tree_o
         L.gridp[H2_PREC_FP64] = grid;
         L.remapp[H2_PREC_FP64] = xcd ? 1 : 0;
         L.flp[H2_PREC_FP64] = 1;
+        L.occp[H2_PREC_FP64] = occ;
       }
   h->couple_mode[prec] = tree_order != 0 ? 1 : 0;
   h->dense_mode[prec] = tree_order != 0 ? 1 : 0;
@@ -1537,8 +1550,8 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
                     L.kind);
       t += line;
       for (int p = 0; p < 3; ++p) {
-        std::snprintf(line, sizeof line, " | %s kc=%d grid=%lld xcd=%d fl=%d %.3fms", pn[p], L.kcp[p],
-                      (long long)L.gridp[p], L.remapp[p], L.flp[p], L.tuned_ms[p]);
+        std::snprintf(line, sizeof line, " | %s kc=%d grid=%lld xcd=%d fl=%d occ=%d %.3fms", pn[p], L.kcp[p],
+                      (long long)L.gridp[p], L.remapp[p], L.flp[p], L.occp[p], L.tuned_ms[p]);
         t += line;
       }
       t += "\n";

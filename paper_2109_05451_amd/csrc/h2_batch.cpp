@@ -292,7 +292,8 @@ int run_blaunch(h2_batch_s* b, const Group& G, const Launch& L, hipStream_t s) {
   if ((L.kc == kWaveRows || L.kc == kWaveTiles) && L.max_rows <= 64) {
     const hipError_t e = launch_wave_rows<double>(b->rt.d_rows + L.row_begin, L.row_count, b->rt.d_colend,
                                                   b->rt.d_in_off, data, G.d_ws, G.d_ws, G.nvp, L.mode,
-                                                  L.max_rows, s, L.grid, L.kc == kWaveTiles, L.remapp[0]);
+                                                  L.max_rows, s, L.grid, L.kc == kWaveTiles, L.remapp[0], nullptr,
+                                                  L.occp[0]);
     if (e != hipSuccess) return hip_fail_b(e, "batch kernel launch");
     return H2_OK;
   }
@@ -531,20 +532,24 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
     for (auto* v : {&G.up, &G.couple, &G.down, &G.dense, &G.out})
       for (Launch& L : *v) {
         float best = 1e30f;
-        int best_kc = L.kc, best_remap = L.remapp[0];
+        int best_kc = L.kc, best_remap = L.remapp[0], best_occ = L.occp[0];
         int64_t best_grid = L.grid;
         for (int kc : kcs)
           for (int64_t gsz : grids)
-            for (int remap = 0; remap < 2; ++remap) {
+            for (int cand = 0; cand < 4; ++cand) {
+            // XCD ranges and the five-waves-per-SIMD form: wave-row kernels only
+            const int remap = cand & 1, occ = cand >> 1 ? 5 : 0;
             const bool wave = kc == kWaveRows || kc == kWaveTiles;
             if (gsz != 0 && gsz >= L.row_count) continue;
             if (wave && L.max_rows > 64) continue;
             if (kc == kWaveTiles && G.nvp != 32 && G.nvp != 64) continue;
-            if (remap && !wave) continue;  // XCD ranges: wave-row kernels only
+            if ((remap || occ) && !wave) continue;
+            if (occ && !wave_occ5(G.nvp, L.max_rows, kc == kWaveTiles)) continue;
             Launch T = L;
             T.kc = kc;
             T.grid = gsz;
             T.remapp[0] = remap;
+            T.occp[0] = occ;
             float tsum = 0.0f;
             for (int rep = 0; rep < 3; ++rep) {
               HIP_TRYB(hipEventRecord(e0, s), "hipEventRecord");
@@ -560,11 +565,13 @@ int h2_batch_tune(h2_batch b, const h2_batch_item* items, void* stream) {
               best_kc = kc;
               best_grid = gsz;
               best_remap = remap;
+              best_occ = occ;
             }
           }
         L.kc = best_kc;
         L.grid = best_grid;
         L.remapp[0] = best_remap;
+        L.occp[0] = best_occ;
         L.tuned_ms[0] = best / 2;
       }
   // the dense rows' schedule, on whole launch sequences (a warm-up, then two
@@ -628,8 +635,9 @@ int h2_batch_plan_info(h2_batch b, char* buf, size_t cap, size_t* needed) {
     int k = 0;
     for (const auto* v : {&G.up, &G.couple, &G.down, &G.dense, &G.out}) {
       for (const Launch& L : *v) {
-        std::snprintf(line, sizeof line, "%s rows=%lld max_rows=%d kc=%d grid=%lld xcd=%d %.3fms\n", names[k],
-                      (long long)L.row_count, L.max_rows, L.kc, (long long)L.grid, L.remapp[0], L.tuned_ms[0]);
+        std::snprintf(line, sizeof line, "%s rows=%lld max_rows=%d kc=%d grid=%lld xcd=%d occ=%d %.3fms\n",
+                      names[k], (long long)L.row_count, L.max_rows, L.kc, (long long)L.grid, L.remapp[0], L.occp[0],
+                      L.tuned_ms[0]);
         t += line;
       }
       ++k;

@@ -115,6 +115,7 @@ struct Launch {
   int64_t gridp[3] = {0, 0, 0};
   int remapp[3] = {0, 0, 0};  // XCD-aware row ranges
   int flp[3] = {1, 1, 1};     // wave-row kernels: read the fragment-ordered copy when there is one
+  int occp[3] = {0, 0, 0};    // wave-row kernels: 5 = the form compiled for five waves per SIMD
   float tuned_ms[3] = {0, 0, 0};  // time of the chosen setting when tuned (two runs)
 };
 
@@ -425,11 +426,20 @@ hipError_t launch_permute_out_rm(const double* Z, const int32_t* pinv, double al
 // workgroups (0: enough for every row at once); remap: XCD-aware row ranges
 constexpr int kWaveRows = 9, kWaveTiles = 10;
 // fl: the fragment-ordered copy of the rows' matrices (rows' fl_off), read
-// instead of `data` when not null; the results are bitwise the same
+// instead of `data` when not null; occ 5: the form compiled for five waves
+// per SIMD where one exists (one 16-vector tile per wave, rows of at most 48
+// outputs), else the default; the results are bitwise the same
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid, bool narrow = false, int remap = 0, const T* fl = nullptr);
+                            hipStream_t s, int64_t grid, bool narrow = false, int remap = 0, const T* fl = nullptr,
+                            int occ = 0);
+// True when launch_wave_rows has a five-waves-per-SIMD form for this pass
+// width, row length and kernel (one 16-vector tile per wave, at most three
+// 16-row tiles)
+inline bool wave_occ5(int nvp, int max_rows, bool narrow) {
+  return max_rows <= 48 && (nvp == 16 || (narrow && (nvp == 32 || nvp == 64)));
+}
 // dst[R.fl_off ...] = the fragment-ordered copy of every row's matrix at src[R.data_off ...]
 template <typename T>
 hipError_t launch_rows_to_fl(const RowDesc* rows, int64_t nrows, const int32_t* colend, const T* src, T* dst,

@@ -216,8 +216,11 @@ __global__ __launch_bounds__(kT) void k_tree(const int2* __restrict__ ranges, Tr
 // wave copies its row's block table into its own LDS region first, so the
 // column cursor (one step per block, dozens of blocks in a coupling or dense
 // row) reads LDS instead of waiting on dependent global loads.
-template <typename T, int NT, int NTW, int MT, bool FL>
-__global__ __launch_bounds__(kT) void k_wave_rows(const RowDesc* __restrict__ rows, int64_t nrows,
+// OCC > 1: compiled for at least OCC waves per SIMD (the register budget
+// shrinks from 128 to 96 at OCC 5, with a few registers spilled): more rows'
+// loads in flight per CU for launches bound by memory latency.
+template <typename T, int NT, int NTW, int MT, bool FL, int OCC>
+__global__ __launch_bounds__(kT, OCC) void k_wave_rows(const RowDesc* __restrict__ rows, int64_t nrows,
                                                   const int32_t* __restrict__ colend,
                                                   const int64_t* __restrict__ in_off, const T* __restrict__ data,
                                                   const double* in, double* out, int mode, int remap) {
@@ -385,19 +388,26 @@ template hipError_t launch_rows_to_fl<float>(const RowDesc*, int64_t, const int3
 template <typename T>
 hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                             const T* data, const double* in, double* out, int nvp, int mode, int max_rows,
-                            hipStream_t s, int64_t grid, bool narrow, int remap, const T* fl) {
+                            hipStream_t s, int64_t grid, bool narrow, int remap, const T* fl, int occ) {
   if (nrows == 0) return hipSuccess;
   if (max_rows > 64) return hipErrorInvalidValue;
   // narrow: a wave per 16-vector tile (NT waves per row, more waves resident); else a wave per row, or
   // two when one wave's accumulators would leave a single wave per SIMD
 #define H2_WR_K(NT, NTW, MT, G)                                                                          \
   do {                                                                                                   \
-    if (fl)                                                                                              \
-      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, true>), G, dim3(kT), 0, s, rows, nrows, colend, in_off, \
+    constexpr bool HI = NTW == 1 && MT <= 3;  /* forms that fit 96 registers with little spilling */     \
+    if (fl && occ == 5 && HI)                                                                            \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, true, HI ? 5 : 1>), G, dim3(kT), 0, s, rows, nrows, \
+                         colend, in_off, fl, in, out, mode, remap);                                      \
+    else if (occ == 5 && HI)                                                                             \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, false, HI ? 5 : 1>), G, dim3(kT), 0, s, rows, nrows, \
+                         colend, in_off, data, in, out, mode, remap);                                    \
+    else if (fl)                                                                                         \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, true, 1>), G, dim3(kT), 0, s, rows, nrows, colend, in_off, \
                          fl, in, out, mode, remap);                                                      \
     else                                                                                                 \
-      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, false>), G, dim3(kT), 0, s, rows, nrows, colend, in_off, \
-                         data, in, out, mode, remap);                                                    \
+      hipLaunchKernelGGL((k_wave_rows<T, NT, NTW, MT, false, 1>), G, dim3(kT), 0, s, rows, nrows, colend, \
+                         in_off, data, in, out, mode, remap);                                            \
   } while (0)
 #define H2_WR(NT, MT)                                                                                    \
   do {                                                                                                   \
@@ -430,10 +440,10 @@ hipError_t launch_wave_rows(const RowDesc* rows, int64_t nrows, const int32_t* c
 }
 template hipError_t launch_wave_rows<double>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const double*,
                                              const double*, double*, int, int, int, hipStream_t, int64_t, bool, int,
-                                             const double*);
+                                             const double*, int);
 template hipError_t launch_wave_rows<float>(const RowDesc*, int64_t, const int32_t*, const int64_t*, const float*,
                                             const double*, double*, int, int, int, hipStream_t, int64_t, bool, int,
-                                            const float*);
+                                            const float*, int);
 
 template <typename T>
 hipError_t launch_tree(const int2* ranges, int64_t nwg, const TreeLevels& L, const RowDesc* rows,

@@ -66,3 +66,10 @@ def test_traffic_only_from_a_summary_of_the_same_kernel_source(tmp_path, monkeyp
     assert bench.measured_traffic("cfg", 1, "coupling", "bf16") is None  # no summary for that precision
     (src / "h2_tree_kernels.hip").write_bytes(b"// more kernels, changed\n")
     assert bench.measured_traffic("cfg", 1, "coupling") is None    # taken on another kernel source
+    # a summary that names the priced kernel's own file: other files may change
+    one = hashlib.md5(b"// kernels\n").hexdigest()
+    (prof / "k_rows_cfg_nv16.md").write_text(f"kernel_source_md5: `{one}` (of: h2_kernels.hip)\n\n"
+                                             "traffic_bytes_per_launch (coupling rows): 2.5e+09\n")
+    assert bench.measured_traffic("cfg", 16, "coupling") == 2.5e9
+    (src / "h2_kernels.hip").write_bytes(b"// kernels, changed\n")
+    assert bench.measured_traffic("cfg", 16, "coupling") is None

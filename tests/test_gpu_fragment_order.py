@@ -3,9 +3,10 @@
 for the low-rank rows).  Wave-row launches that read them get the same MFMA
 operands in the same order as from the column-major data, so the products
 must be bitwise those of a handle without the copies under the same fixed
-kernel settings: a wave per row and a wave per 16-vector tile,
-one workgroup per row and a persistent grid smaller than the row count, with
-and without the XCD-aware row ranges.  The operators cover ranks whose row
+kernel settings: a wave per row and a wave per 16-vector tile (each also in
+its form compiled for five waves per SIMD), one workgroup per row and a
+persistent grid smaller than the row count, with and without the XCD-aware
+row ranges.  The operators cover ranks whose row
 tiles are ragged (25 = 16 + 9, 27 = 16 + 11) or whole (16, 64), odd leaf
 sizes, and column counts that are not multiples of eight (the copy's
 column-major tail).  FP64 results are the oracle's within 1e-12 * B."""
@@ -50,7 +51,7 @@ def test_fragment_order_bitwise(name):
             for g in (tuned, plain):
                 g.set_sweeps(prec, False)  # per-level launches: every phase on the row kernels
                 g.set_schedule(prec, 0)
-            kcs = (9, 10) if nv > 16 else (9,)
+            kcs = (9, 10, 11, 12) if nv > 16 else (9, 11)
             for kc in kcs:
                 for grid in (0, 24):
                     for xcd in (False, True):

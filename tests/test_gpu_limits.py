@@ -78,7 +78,7 @@ def test_ranks_33_to_36_every_kernel(seed):
     X = rng.integers(-2, 3, size=(g.n, 64)).astype(np.float64)
     Y0 = rng.integers(-2, 3, size=(g.n, 64)).astype(np.float64)
     want = ref.gemv(X, op="N", alpha=2.0, beta=-1.0, Y=Y0)
-    for kc in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 32, 64):
+    for kc in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 32, 64):
         for grid in (0, 8, 24, 1024):  # 8, 24: persistent grids walking several rows each
             for xcd in ((False, True) if grid in (8, 24) else (False,)):
                 g.tune_set("fp64", kc, grid, xcd, 0)

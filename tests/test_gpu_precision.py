@@ -151,7 +151,7 @@ def test_launch_settings_bitwise(prec):
         if prec == "fp64":
             want, B = ref.gemv(X), ref.gemv(X, absval=True)
             assert np.all(np.abs(base - want) <= 1e-12 * B)
-        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 32, 64)
+        kcs = (64,) if prec == "bf16" else (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 32, 64)
         for kc in kcs:
             for grid in GRIDS:
                 for xcd in (False, True):
@@ -184,7 +184,7 @@ def test_persistent_grids_walk_rows_against_oracle(prec, rank):
     X = h2gen.vectors(g.n, 64, 14)
     want, B = ref.gemv(X), ref.gemv(X, absval=True)
     tol = {"fp64": 1e-12, "fp32": TOL32, "bf16": TOL16}[prec]
-    kcs = (64,) if prec == "bf16" else (0, 5, 8, 9, 10, 32, 64)
+    kcs = (64,) if prec == "bf16" else (0, 5, 8, 9, 10, 11, 12, 32, 64)
     first = None
     for kc in kcs:
         for grid in (8, 24):
