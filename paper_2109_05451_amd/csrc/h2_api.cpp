@@ -258,6 +258,7 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
   const int64_t q = P.q, n = P.n;
   const int64_t* lp = P.level_ptr;
   h->n = n; h->q = q; h->nnodes = P.nnodes; h->nleaves = P.nleaves; h->leaf0 = P.leaf0;
+  h->lmin = first_coupling_level(P);
   h->shared = !(P.flags & 1u);
   h->lv.resize(q + 1);
   for (int64_t l = 0; l <= q; ++l) {
@@ -299,7 +300,10 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
     emit_rows_N(lay, B, &R);
     Plan& plan = h->planN;
     add_stream_phase(h, R.up[0], ARR_TRANS, BUF_XT, BUF_XH, MODE_STORE, false, plan.up);
-    for (int64_t hh = 1; hh <= q; ++hh) add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
+    for (int64_t hh = 1; hh <= q; ++hh) {
+      add_stream_phase(h, R.up[hh], ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
+      plan.up.back().level = q - hh;
+    }
     add_stream_phase(h, R.couple, ARR_MAT, BUF_XH, BUF_YH, MODE_STORE, true, plan.couple);
     {
       // the leaf level's coupling rows are the last ones emitted
@@ -321,7 +325,10 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
       for (auto* v : {&plan.dense_loc, &plan.dense2_loc})
         for (Launch& L : *v) L.lowrank = false;
     }
-    for (int64_t l = 1; l <= q; ++l) add_stream_phase(h, R.down[l - 1], ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
+    for (int64_t l = 1; l <= q; ++l) {
+      add_stream_phase(h, R.down[l - 1], ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
+      plan.down.back().level = l - 1;
+    }
     {
       // two halves with the same mix of long and short rows (longest first in each)
       const std::vector<size_t> o = order_by_work(R.dense);
@@ -373,6 +380,7 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
         rows.push_back(std::move(r));
       }
       add_stream_phase(h, rows, ARR_TRANS, BUF_XH, BUF_XH, MODE_STORE, false, plan.up);
+      plan.up.back().level = l - 1;
     }
     rows.clear();
     for (int64_t l = 0; l <= q; ++l) {
@@ -392,6 +400,7 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
         rows.push_back({oF + lay.foff(c, l), hoff[c], H, H, (int32_t)kr[l],
                         {BlockRef{0, hoff[P.parent[c]], (int32_t)kr[l - 1], 0}}});
       add_stream_phase(h, rows, ARR_MAT, BUF_YH, BUF_YH, MODE_ACCUM, false, plan.down);
+      plan.down.back().level = l - 1;
     }
     rows.clear();
     std::vector<std::vector<BlockRef>> by_col(P.nleaves);
@@ -582,6 +591,11 @@ int load_common(const uint8_t* buf, int64_t len, int device, h2_handle* out, con
 // copy (w.xh32, converted from w.xh after the upsweep).
 // out_ptr: an output buffer in place of the launch's own (the multi-vector
 // leaf expansion into w.zx).
+// A sweep transfer launch above the first level with coupling blocks: its
+// parents' x^ is never read (upsweep) or their y^ is zero (downsweep), so it
+// adds only exact zeros and does not run.
+bool skipped(const h2_op_s* h, const Launch& L) { return L.level >= 0 && L.level < h->lmin; }
+
 int run_launch(h2_op_s* h, const Workspace& w, const Launch& L, int nv, const Epilogue& ep, hipStream_t s,
                int nvp = 0, int mode_override = -1, int prec = H2_PREC_FP64, bool x32 = false,
                double* out_ptr = nullptr) {
@@ -860,7 +874,7 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
     STEP(run_tree(h, w, h->tree_up, nvp, prec, s));
   } else {
     for (size_t i = 0; i < plan.up.size(); ++i) {
-      STEP(run_launch(h, w, plan.up[i], nv, ep, s, nvp, -1, prec));
+      if (!skipped(h, plan.up[i])) STEP(run_launch(h, w, plan.up[i], nv, ep, s, nvp, -1, prec));
       if (split && i == 0) {  // the leaf level's x^ is complete
         HIP_TRY(hipEventRecord(w.ev_deep, s), "hipEventRecord(deep)");
         HIP_TRY(hipStreamWaitEvent(w.side2, w.ev_deep, 0), "hipStreamWaitEvent(deep)");
@@ -899,7 +913,7 @@ int gemv_pass(h2_op_s* h, const Workspace& w, bool trans, double alpha, const do
     for (size_t i = 0; i < plan.down.size(); ++i) {
       if (split && i + 1 == plan.down.size())  // the leaf level's y^ needs its coupling rows
         HIP_TRY(hipStreamWaitEvent(s, w.ev_deep_done, 0), "hipStreamWaitEvent(deep done)");
-      STEP(run_launch(h, w, plan.down[i], nv, ep, s, nvp, -1, prec));
+      if (!skipped(h, plan.down[i])) STEP(run_launch(h, w, plan.down[i], nv, ep, s, nvp, -1, prec));
     }
   }
   if (zx && !fused) STEP(run_launch(h, w, plan.out, nv, ep, s, nvp, MODE_STORE, prec, false, w.zx));
@@ -1341,6 +1355,7 @@ int h2_tune(h2_handle h, int64_t nv, int prec, void* stream) {
   auto tune_list = [&](std::vector<Launch>& v, float* total, bool couple = false) -> int {
     *total = 0.0f;
     for (Launch& L : v) {
+      if (skipped(h, L)) continue;  // never runs
       float t = 0.0f;
       const int r = tune_one(L, -1, &t, couple);
       if (r != H2_OK) return r;
@@ -1538,6 +1553,9 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
   std::string t;
   char line[256];
   const char* pn[3] = {"fp64", "fp32", "bf16"};
+  std::snprintf(line, sizeof line, "first level with coupling blocks: %lld (sweep transfers above it skipped)\n",
+                (long long)h->lmin);
+  t += line;
   for (int p = 0; p < 3; ++p) {
     const char* cmn[2] = {"longest first", "tree order"};
     std::snprintf(line, sizeof line, "%s: coupling rows %s, dense rows %s\n", pn[p], cmn[h->couple_mode[p]],
@@ -1554,6 +1572,7 @@ int h2_plan_info(h2_handle h, char* buf, size_t cap, size_t* needed) {
                       (long long)L.gridp[p], L.remapp[p], L.flp[p], L.occp[p], L.tuned_ms[p]);
         t += line;
       }
+      if (skipped(h, L)) t += " | skipped (above the first coupling level)";
       t += "\n";
     }
   };

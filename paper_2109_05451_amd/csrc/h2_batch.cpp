@@ -200,8 +200,13 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
       if (op_group[i] != gi) continue;
       RowsN R;
       emit_rows_N(lay[i], base[i], &R);
-      for (size_t h = 0; h < R.up.size(); ++h) up[h].insert(up[h].end(), R.up[h].begin(), R.up[h].end());
-      for (size_t d = 0; d < R.down.size(); ++d) down[d].insert(down[d].end(), R.down[d].begin(), R.down[d].end());
+      // transfer levels above the operator's first level with coupling blocks
+      // are left out (x^ there is never read, y^ there is zero)
+      const int64_t lmin = first_coupling_level(P[i]), qi = P[i].q;
+      for (size_t h = 0; h < R.up.size(); ++h)
+        if (h == 0 || qi - (int64_t)h >= lmin) up[h].insert(up[h].end(), R.up[h].begin(), R.up[h].end());
+      for (size_t d = 0; d < R.down.size(); ++d)
+        if ((int64_t)d >= lmin) down[d].insert(down[d].end(), R.down[d].begin(), R.down[d].end());
       couple.insert(couple.end(), R.couple.begin(), R.couple.end());
       dense.insert(dense.end(), R.dense.begin(), R.dense.end());
       outr.insert(outr.end(), R.out.begin(), R.out.end());

@@ -117,6 +117,9 @@ struct Launch {
   int flp[3] = {1, 1, 1};     // wave-row kernels: read the fragment-ordered copy when there is one
   int occp[3] = {0, 0, 0};    // wave-row kernels: 5 = the form compiled for five waves per SIMD
   float tuned_ms[3] = {0, 0, 0};  // time of the chosen setting when tuned (two runs)
+  // sweep transfer launches: the level of the parent nodes (upsweep: whose
+  // x^ it computes; downsweep: whose y^ it pushes down); -1 for other launches
+  int64_t level = -1;
 };
 
 // The launch sequence of one operation (op 'N' or 'T').
@@ -206,6 +209,13 @@ struct RowSpec {
   int32_t nrows;
   std::vector<BlockRef> blks;
 };
+
+// First level with coupling blocks, q + 1 if there is none.
+inline int64_t first_coupling_level(const Parsed& P) {
+  for (int64_t l = 0; l <= P.q; ++l)
+    if (P.nadm[l] > 0) return l;
+  return P.q + 1;
+}
 
 // Per-operator offsets used to emit rows.
 struct OpLayout {
@@ -302,6 +312,9 @@ bool prepared(h2_op_s* h, int prec);
 struct h2_op_s {
   int device = 0;
   int64_t n = 0, q = 0, nnodes = 0, nleaves = 0, leaf0 = 0;
+  // first level with coupling blocks (q + 1 if none): above it x^ is never
+  // read and y^ is zero, so the per-level sweeps skip those transfer levels
+  int64_t lmin = 0;
   int64_t H = 0;  // rows of the vector trees (sum of per-node max rank)
   bool shared = true;
   std::vector<h2::LevelInfo> lv;
