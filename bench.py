@@ -270,9 +270,11 @@ def latency_gpu(g, X, Y, nv, calls, torch):
 
 def small_operator_latency(torch, calls: int = 200) -> dict:
     """Latency of one product on the 4096-point 2D operator (leaf 64, 4x4
-    Chebyshev, nv = 1; about 22 MB, so it lives in the on-die cache): HIP
-    events around each call on a stream of its own, launched one by one and
-    replayed from a captured HIP graph (h2_graph), p50 / p99 over `calls`."""
+    Chebyshev, nv = 1; about 22 MB, so it lives in the on-die cache), after
+    h2_tune has chosen its schedule: HIP events around each call on a stream
+    of its own, launched one by one and replayed from a captured HIP graph
+    (h2_graph), p50 / p99 over `calls`."""
+    import re
     import h2gen
     from paper_2109_05451_amd import H2Operator
     buf = h2gen.build_config("c1_2d_4096")
@@ -281,8 +283,11 @@ def small_operator_latency(torch, calls: int = 200) -> dict:
     X = torch.from_numpy(np.asfortranarray(h2gen.vectors(n, 1, 2001))).cuda()
     Y = torch.empty((1, n), dtype=torch.float64, device="cuda").t()
     stream = torch.cuda.Stream()
+    g.tune(1, "fp64", stream.cuda_stream)  # the streaming path's schedule, timed on whole products
+    sched = re.search(r"fp64: streaming dense schedule (\d)", g.plan_info())
     out = {"workload": "c1_2d_4096: " + WORKLOADS["c1_2d_4096"] + ", nv=1",
-           "launches_per_product": launches_per_product(g)}
+           "launches_per_product": launches_per_product(g),
+           "schedule": int(sched.group(1)) if sched else None}
     for mode in ("launches", "graph"):
         g.graph(mode == "graph")
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
