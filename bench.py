@@ -49,14 +49,15 @@ def kernel_source_md5(files=KERNEL_SOURCES) -> str:
     return m.hexdigest()
 
 
-def measured_traffic(config: str, nv: int, phase: str, precision: str = "fp64"):
+def measured_traffic(config: str, nv: int, phase: str, precision: str = "fp64", name: str = None):
     """HBM bytes per launch of the dominant kernel (the launch of ``phase`` rows)
     from the committed rocprofv3 summary (FETCH_SIZE x calibration + WRITE_SIZE),
     or None when there is no summary for this workload, precision and phase or
-    the kernel sources changed since it was taken."""
+    the kernel sources changed since it was taken.  ``name``: the summary's
+    file name under profiles/ instead of the one derived from the workload."""
     import re
     suffix = "" if precision == "fp64" else "_" + precision
-    path = os.path.join(ROOT, "profiles", f"k_rows_{config}_nv{nv}{suffix}.md")
+    path = os.path.join(ROOT, "profiles", name or f"k_rows_{config}_nv{nv}{suffix}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -439,8 +440,9 @@ def bench_batch(args, torch):
                                    "autotuned, HIP graph replay",
                        "operators": len(specs), "total_n": info["total_n"], "launches_per_call": info["launches"],
                        "flops_per_call": flops, "alg_bytes_per_call": bytes_},
-            "roofline": hbm_roofline(bytes_, t_ms, "whole batched call (every merged launch; HBM-bound at about "
-                                                   f"{flops / bytes_:.1f} flop/B)"),
+            "roofline": dict(hbm_roofline(bytes_, t_ms, "whole batched call (every merged launch; HBM-bound at about "
+                                                        f"{flops / bytes_:.1f} flop/B)"),
+                             traffic=measured_traffic("c4_batch", 0, "whole call", name="batch_c4_256ops.md")),
             "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
                            "p99": round(float(np.percentile(per, 99)), 4)}}
 
