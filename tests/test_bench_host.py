@@ -73,3 +73,35 @@ def test_traffic_only_from_a_summary_of_the_same_kernel_source(tmp_path, monkeyp
     assert bench.measured_traffic("cfg", 16, "coupling") == 2.5e9
     (src / "h2_kernels.hip").write_bytes(b"// kernels, changed\n")
     assert bench.measured_traffic("cfg", 16, "coupling") is None
+
+
+def test_plan_description_parsing():
+    """The tuned coupling time and the launch count read from h2_plan_info's
+    text: the schedule decides which coupling lines count; launches marked
+    skipped do not count."""
+    info = "\n".join([
+        "first level with coupling blocks: 3 (sweep transfers above it skipped)",
+        "fp64: coupling rows longest first, dense rows longest first",
+        "fp64: dense schedule 0 (tuned products 3.0 / 3.1 / 3.1 / 3.2 ms)",
+        "fp32: dense schedule 3 (tuned products 2.7 / 2.7 / 2.7 / 2.6 ms)",
+        "up rows=4 max_rows=36 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=0 occ=0 0.010ms | skipped (above the first "
+        "coupling level)",
+        "up rows=8 max_rows=36 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=0 occ=0 0.012ms",
+        "couple rows=100 max_rows=36 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=1 occ=5 1.127ms | fp32 kc=9 grid=0 xcd=0 "
+        "fl=1 occ=0 0.950ms",
+        "couple_deep rows=60 max_rows=36 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=1 occ=0 0.700ms | fp32 kc=9 grid=0 "
+        "xcd=0 fl=1 occ=0 0.600ms",
+        "couple_rest rows=40 max_rows=36 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=1 occ=5 0.400ms | fp32 kc=9 grid=0 "
+        "xcd=0 fl=0 occ=0 0.300ms",
+        "down rows=8 max_rows=36 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=0 occ=0 0.011ms",
+        "dense1 rows=50 max_rows=64 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=0 occ=0 0.500ms",
+        "out rows=50 max_rows=64 kind=0 | fp64 kc=9 grid=0 xcd=0 fl=0 occ=0 0.080ms",
+    ])
+    assert abs(bench.tuned_coupling_ms(info, "fp64") - 1.127) < 1e-9       # schedule 0: the one launch
+    assert abs(bench.tuned_coupling_ms(info, "fp32") - 0.9) < 1e-9         # schedule 3: deep + rest
+
+    class G:
+        def plan_info(self):
+            return info
+    # permutation + up (one of two runs) + couple + down + dense1 + out
+    assert bench.launches_per_product(G()) == 1 + 1 + 1 + 1 + 1 + 1
