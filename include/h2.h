@@ -225,8 +225,9 @@ int h2_reserve(h2_handle h, int64_t nv_max);
  * Results do not depend on the choice: every candidate sums each output in
  * the same order, so they are bitwise identical.  For nv <= 4 outside BF16
  * (the streaming path) it times the four schedules of h2_set_schedule on
- * whole products (back-to-back products for about 4 ms per schedule, 3 to
- * 64 of them) and keeps the fastest (by the same 1% rule).  Synchronous;
+ * whole products (the median of 3 to 63 products timed one at a time, for
+ * about 4 ms per schedule) and keeps the fastest (by the same 1% rule).
+ * Synchronous;
  * must not run concurrently with other calls on the handle (it uses the
  * handle's workspace).
  * Errors: H2_EINVAL (null handle, nv < 0, unknown precision), H2_ENOMEM,

@@ -1138,39 +1138,40 @@ int tune_stream_schedule(h2_op_s* h, int64_t nv, int prec, void* stream) {
     set_error("tuning buffers");
     return done(H2_ENOMEM);
   }
-  // each schedule: a warm-up product, then back-to-back products for about
-  // 4 ms (3 to 64 of them; a product of ~0.1 ms varies by more than the
-  // schedules differ when timed a few times) on the stream, averaged
+  // each schedule: two warm-up products, then products one at a time (each
+  // waited for) for about 4 ms, 3 to 63 of them, and the median time: a
+  // product of ~0.1 ms varies by more than the schedules differ when timed
+  // a few times, and the latency of one product is what a schedule changes
   const int orig = h->sched1[prec];
-  auto timed = [&](int reps, float* per) -> int {
+  auto timed = [&](float* ms) -> int {
     if (hipEventRecord(e0, s) != hipSuccess) return H2_EHIP;
-    for (int r = 0; r < reps; ++r) {
-      const int rr = gemv_ws(h, h->ws, false, 1.0, X, h->n, nvc, 0.0, Y, h->n, prec, s);
-      if (rr != H2_OK) return rr;
-    }
-    float ms = 0.0f;
+    const int rr = gemv_ws(h, h->ws, false, 1.0, X, h->n, nvc, 0.0, Y, h->n, prec, s);
+    if (rr != H2_OK) return rr;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess) {
       set_error("timing the streaming schedules failed");
       return H2_EHIP;
     }
-    *per = ms / (float)reps;
     return H2_OK;
   };
   float best = 1e30f;
   int best_s = orig;
   for (int sc = 0; sc < 4; ++sc) {
     h->sched1[prec] = sc;
-    float t1 = 0.0f, t = 0.0f;
-    if ((rc = timed(1, &t1)) != H2_OK || (rc = timed(1, &t1)) != H2_OK) {
+    float t1 = 0.0f;
+    if ((rc = timed(&t1)) != H2_OK || (rc = timed(&t1)) != H2_OK) {
       h->sched1[prec] = orig;
       return done(rc);
     }
-    const int reps = (int)std::min(64.0f, std::max(3.0f, std::ceil(4.0f / std::max(t1, 1e-3f))));
-    if ((rc = timed(reps, &t)) != H2_OK) {
-      h->sched1[prec] = orig;
-      return done(rc);
-    }
+    const int reps = (int)std::min(63.0f, std::max(3.0f, std::ceil(4.0f / std::max(t1, 1e-3f))));
+    std::vector<float> ts((size_t)reps);
+    for (int r = 0; r < reps; ++r)
+      if ((rc = timed(&ts[(size_t)r])) != H2_OK) {
+        h->sched1[prec] = orig;
+        return done(rc);
+      }
+    std::nth_element(ts.begin(), ts.begin() + reps / 2, ts.end());
+    const float t = ts[(size_t)reps / 2];
     h->sched1_ms[prec][sc] = t;
     if (t < best * kScheduleGain) {
       best = t;
