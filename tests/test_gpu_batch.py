@@ -158,6 +158,14 @@ def test_batch_per_operator_widths():
         Yd = [to_dev(Y) for Y in Y0s]
         if rep == 1:
             batch.tune(Xd, [to_dev(Y) for Y in Y0s], alphas, betas)
+            # the plan description: one line per merged launch of every group
+            # (each group's two permutations aside), with the tuned times
+            info = batch.plan_info()
+            groups = [l for l in info.splitlines() if l.startswith("group nvp=")]
+            rows = [l for l in info.splitlines() if " rows=" in l]
+            assert len(groups) >= 3 and info.startswith("schedule ")
+            assert len(rows) == batch.info()["launches"] - 2 * len(groups)
+            assert all(float(l.rsplit(" ", 1)[1].rstrip("ms")) > 0 for l in rows)
         batch.gemv(Xd, Yd, alphas, betas)
         torch.cuda.synchronize()
         check(refs, kinds, Xs, Y0s, nvs, alphas, betas, Yd)
