@@ -338,6 +338,8 @@ int h2_set_sweeps(h2_handle h, int prec, int fused);
  * precision read it (the dense rows' FP64 entries too); enable == 0: read
  * the column-major data, and free copies that no launch reads any more.
  * Results are bitwise the same either way; h2_tune chooses per launch.
+ * Synchronizes the device and drops the captured graphs; must not run
+ * concurrently with other calls on the handle.
  * Errors: H2_EINVAL (null handle, precision other than FP64 or FP32),
  * H2_ENOMEM, H2_EHIP. */
 int h2_set_fragment_order(h2_handle h, int prec, int enable);
