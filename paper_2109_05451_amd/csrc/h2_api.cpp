@@ -347,13 +347,6 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
       return H2_EUNSUPPORTED;
     }
     plan.out = outl[0];
-    // regions of the fragment-ordered copies (made by h2_tune)
-    std::map<FlKey, int64_t> keys;
-    for (const auto* v : {&plan.up, &plan.couple, &plan.down, &plan.dense, &plan.dense2, &plan.couple_loc,
-                          &plan.dense_loc, &plan.dense2_loc, &plan.couple_deep, &plan.couple_rest})
-      for (const Launch& L : *v)
-        if (L.kind == KIND_STREAM) place_fl(h->rt, L.row_begin, L.row_begin + L.row_count, L.arr, &keys, &h->n_fl);
-    place_fl(h->rt, plan.out.row_begin, plan.out.row_begin + plan.out.row_count, plan.out.arr, &keys, &h->n_fl);
   }
   std::vector<int2> tree_ranges;
   h->tree_ok = build_tree_groups(h, P, lay, &tree_ranges);
@@ -693,8 +686,26 @@ int prepare_f32(h2_op_s* h) {
 // FP64 of every row, and for FP32 (after prepare_f32) of the low-rank rows.
 int prepare_fl(h2_op_s* h, int prec) {
   std::lock_guard<std::mutex> lock(h->prep_mu);
-  if (h->n_fl == 0 || !h->mfma_ok) return H2_OK;
+  if (!h->mfma_ok) return H2_OK;
   const Plan& p = h->planN;
+  if (!h->fl_placed) {
+    // the copies' regions, in the rows' fl_off (the device row table is
+    // rewritten; nothing runs on the handle meanwhile)
+    FlKeys keys;
+    keys.reserve(2 * h->rt.rows.size());
+    int64_t n_fl = 0;
+    for (const auto* v : {&p.up, &p.couple, &p.down, &p.dense, &p.dense2, &p.couple_loc, &p.dense_loc,
+                          &p.dense2_loc, &p.couple_deep, &p.couple_rest})
+      for (const Launch& L : *v)
+        if (L.kind == KIND_STREAM) place_fl(h->rt, L.row_begin, L.row_begin + L.row_count, L.arr, &keys, &n_fl);
+    place_fl(h->rt, p.out.row_begin, p.out.row_begin + p.out.row_count, p.out.arr, &keys, &n_fl);
+    if (!h->rt.rows.empty())
+      HIP_TRY(hipMemcpy(h->rt.d_rows, h->rt.rows.data(), sizeof(RowDesc) * h->rt.rows.size(), hipMemcpyHostToDevice),
+              "hipMemcpy(row table)");
+    h->n_fl = n_fl;
+    h->fl_placed = true;
+  }
+  if (h->n_fl == 0) return H2_OK;
   // one copy: every launch's rows (FP64), or the low-rank ones (FP32); the
   // handle keeps it only when every relayout ran
   auto make = [&](void* d, bool fp32) -> hipError_t {

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "h2.h"
@@ -258,13 +259,12 @@ int64_t row_work(const RowSpec& r);
 // same matrix (array, offset and shape) share one region; regions start at
 // even offsets.  *n_fl grows by the elements placed.  `keys` carries the
 // placed regions between calls.
-struct FlKey {
-  int arr;
-  int64_t data_off;
+struct FlRegion {
+  int64_t fl_off;
   int32_t nrows, ncols;
-  bool operator<(const FlKey& o) const;
 };
-void place_fl(RowTables& t, int64_t begin, int64_t end, int arr, std::map<FlKey, int64_t>* keys, int64_t* n_fl);
+using FlKeys = std::unordered_map<int64_t, FlRegion>;  // key: 2 * data_off + array
+void place_fl(RowTables& t, int64_t begin, int64_t end, int arr, FlKeys* keys, int64_t* n_fl);
 
 // Per-product scratch: X~ and the dense partial (n x cap), x^ and y^
 // (H x cap) in doubles; the streaming path uses them column-major with up
@@ -331,7 +331,8 @@ struct h2_op_s {
   void* d_trans16 = nullptr;
   // fragment-ordered copies of the op-'N' rows (FP64 every row, FP32 the
   // low-rank rows) at the rows' fl_off, read by the wave-row kernels; made by
-  // h2_tune on the multi-vector path
+  // h2_tune on the multi-vector path (the regions are placed then too)
+  bool fl_placed = false;
   int64_t n_fl = 0;
   double* d_fl = nullptr;
   float* d_fl32 = nullptr;

@@ -165,20 +165,19 @@ void append_row(RowTables& t, const RowSpec& r) {
   t.rows.push_back(R);
 }
 
-bool FlKey::operator<(const FlKey& o) const {
-  if (arr != o.arr) return arr < o.arr;
-  if (data_off != o.data_off) return data_off < o.data_off;
-  if (nrows != o.nrows) return nrows < o.nrows;
-  return ncols < o.ncols;
-}
-
-void place_fl(RowTables& t, int64_t begin, int64_t end, int arr, std::map<FlKey, int64_t>* keys, int64_t* n_fl) {
+void place_fl(RowTables& t, int64_t begin, int64_t end, int arr, FlKeys* keys, int64_t* n_fl) {
   for (int64_t i = begin; i < end; ++i) {
     RowDesc& R = t.rows[i];
     const int32_t ncols = R.blk_end > R.blk_begin ? t.colend[R.blk_end - 1] : 0;
-    const auto ins = keys->emplace(FlKey{arr, R.data_off, R.nrows, ncols}, *n_fl);
-    R.fl_off = ins.first->second;
-    if (ins.second) *n_fl += ((int64_t)R.nrows * ncols + 1) / 2 * 2;
+    const int64_t size = ((int64_t)R.nrows * ncols + 1) / 2 * 2;
+    const auto ins = keys->emplace(2 * R.data_off + arr, FlRegion{*n_fl, R.nrows, ncols});
+    if (!ins.second && (ins.first->second.nrows != R.nrows || ins.first->second.ncols != ncols)) {
+      R.fl_off = *n_fl;  // the same offset with another shape: a region of its own
+      *n_fl += size;
+      continue;
+    }
+    R.fl_off = ins.first->second.fl_off;
+    if (ins.second) *n_fl += size;
   }
 }
 
