@@ -284,14 +284,6 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
   h->H = H;
   auto msz = [&](int64_t c) { return (int32_t)(P.hi[c] - P.lo[c]); };
 
-  // ---- transposed copies of the bases (for the upsweep products)
-  if (ntrans > 0) {
-    std::vector<double> tr(ntrans);
-    build_transposed(buf, lay, tr.data());
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&h->d_trans), ntrans * sizeof(double)), "hipMalloc(trans)");
-    HIP_TRY(hipMemcpy(h->d_trans, tr.data(), ntrans * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy(trans)");
-  }
-
   // ---- plan for op 'N': rows from the shared emitter (column-major layout)
   {
     RowsN R;
@@ -299,6 +291,25 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
     B.ld_x = n;
     B.ld_h = H;
     emit_rows_N(lay, B, &R);
+    {
+      // room for every row the plans append: the sweeps of both ops, three
+      // orders of the coupling rows, two of the dense rows
+      size_t nr = 0, nb = 0;
+      auto count = [&](const std::vector<RowSpec>& v, size_t copies) {
+        for (const RowSpec& r : v) {
+          nr += copies;
+          nb += copies * r.blks.size();
+        }
+      };
+      for (const auto& v : R.up) count(v, 2);
+      for (const auto& v : R.down) count(v, 2);
+      count(R.out, 2);
+      count(R.couple, 3);
+      count(R.dense, 2);
+      h->rt.rows.reserve(nr);
+      h->rt.colend.reserve(nb);
+      h->rt.in_off.reserve(nb);
+    }
     Plan& plan = h->planN;
     add_stream_phase(h, R.up[0], ARR_TRANS, BUF_XT, BUF_XH, MODE_STORE, false, plan.up);
     for (int64_t hh = 1; hh <= q; ++hh) {
@@ -482,6 +493,23 @@ int build_handle(const uint8_t* buf, const Parsed& P, h2_op_s* h, const double* 
       HIP_TRY(hipMemcpy(reinterpret_cast<uint8_t*>(h->d_mat) + (P.off_D - P.off_U), d_dense, P.off_end - P.off_D,
                         hipMemcpyDeviceToDevice),
               "hipMemcpy(dense blocks)");
+  }
+  // ---- transposed copies of the bases (for the upsweep products), made on
+  // the device from the uploaded matrix data
+  if (ntrans > 0) {
+    std::vector<TransTask> tasks;
+    transpose_tasks(lay, &tasks);
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&h->d_trans), ntrans * sizeof(double)), "hipMalloc(trans)");
+    HIP_TRY(hipMemset(h->d_trans, 0, ntrans * sizeof(double)), "hipMemset(trans)");
+    if (!tasks.empty()) {
+      TransTask* d_tasks = nullptr;
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&d_tasks), sizeof(TransTask) * tasks.size()), "hipMalloc(tasks)");
+      hipError_t e = hipMemcpy(d_tasks, tasks.data(), sizeof(TransTask) * tasks.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = launch_transpose_tasks(d_tasks, (int64_t)tasks.size(), h->d_mat, h->d_trans, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      (void)hipFree(d_tasks);
+      if (e != hipSuccess) return hip_fail(e, "transposed basis copies");
+    }
   }
   h->prefix.assign((size_t)(P.off_U + 7) / 8, 0);
   std::memcpy(h->prefix.data(), buf, (size_t)P.off_U);

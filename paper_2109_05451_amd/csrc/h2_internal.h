@@ -251,6 +251,16 @@ struct RowsN {
 };
 
 int make_layout(const Parsed& P, OpLayout* L);
+// The transposed copies of the bases as a list of blocks: the column-major
+// rows x cols block at element src of the matrix array goes, transposed
+// (cols x rows, column-major), to element dst of the transposed array
+// (leaf bases, then transfers; both bases when they are separate).
+struct TransTask {
+  int64_t src, dst;
+  int32_t rows, cols;
+};
+void transpose_tasks(const OpLayout& L, std::vector<TransTask>* out);
+// The transposed array on the host (zeros where no block lands).
 void build_transposed(const uint8_t* buf, const OpLayout& L, double* tr);
 void emit_rows_N(const OpLayout& L, const RowBases& B, RowsN* R);
 void append_row(RowTables& t, const RowSpec& r);
@@ -424,6 +434,10 @@ constexpr int kPermTile = 64;
 hipError_t launch_batch_permute(const BatchItem* items, const int32_t* tile_op, const int32_t* tile_j0,
                                 int64_t ntiles, const int32_t* pinv, double* ws, int nvp, bool out, hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+// The transposed basis copies on the device (h2_load_kernels.hip): every
+// task's block of `mat` transposed into `trans` (which the caller zeroed).
+hipError_t launch_transpose_tasks(const TransTask* tasks, int64_t ntasks, const double* mat, double* trans,
+                                  hipStream_t s);
 // BF16 path (data: __bf16, rows stored row-major; see the kernel file)
 hipError_t launch_rows_mfma_bf16(const RowDesc* rows, int64_t nrows, const int32_t* colend, const int64_t* in_off,
                                  const void* data, const void* in, bool in16, int64_t ldb, void* out, bool out16,

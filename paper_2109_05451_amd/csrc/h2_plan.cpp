@@ -64,31 +64,34 @@ int64_t OpLayout::foff(int64_t c, int64_t l) const {
   return P->fbase[l] + (c - P->level_ptr[l]) * P->kcol[l] * P->kcol[l - 1];
 }
 
-void build_transposed(const uint8_t* buf, const OpLayout& L, double* tr) {
+void transpose_tasks(const OpLayout& L, std::vector<TransTask>* out) {
   const Parsed& P = *L.P;
   const int64_t q = P.q;
-  std::fill(tr, tr + L.ntrans, 0.0);
-  const double* U = reinterpret_cast<const double*>(buf + P.off_U);
-  const double* E = reinterpret_cast<const double*>(buf + P.off_E);
-  const double* V = L.shared ? U : reinterpret_cast<const double*>(buf + P.off_V);
-  const double* F = L.shared ? E : reinterpret_cast<const double*>(buf + P.off_F);
+  out->clear();
   for (int pass = 0; pass < (L.shared ? 1 : 2); ++pass) {
-    const double* B = pass ? V : U;
-    const double* T = pass ? F : E;
     const int64_t* k = pass ? P.kcol : P.krow;
+    const int64_t ob = pass ? L.oV : L.oU, ot = pass ? L.oF : L.oE;
     const int64_t tb = pass ? L.tVT : L.tUT, tt = pass ? L.tFT : L.tET;
-    for (int64_t t = P.leaf0; t < P.nnodes; ++t) {  // B_t is m x k; B_t^T is k x m
+    for (int64_t t = P.leaf0; t < P.nnodes; ++t) {  // leaf basis: m x k
       const int64_t m = P.hi[t] - P.lo[t], base = P.lo[t] * k[q];
-      for (int64_t a = 0; a < k[q]; ++a)
-        for (int64_t i = 0; i < m; ++i) tr[tb + base + a + k[q] * i] = B[base + i + m * a];
+      out->push_back({ob + base, tb + base, (int32_t)m, (int32_t)k[q]});
     }
     for (int64_t l = 1; l <= q; ++l)
-      for (int64_t c = P.level_ptr[l]; c < P.level_ptr[l + 1]; ++c) {  // T_c is k[l] x k[l-1]
+      for (int64_t c = P.level_ptr[l]; c < P.level_ptr[l + 1]; ++c) {  // transfer: k[l] x k[l-1]
         const int64_t base = pass ? L.foff(c, l) : L.eoff(c, l);
-        for (int64_t b = 0; b < k[l - 1]; ++b)
-          for (int64_t a = 0; a < k[l]; ++a) tr[tt + base + b + k[l - 1] * a] = T[base + a + k[l] * b];
+        out->push_back({ot + base, tt + base, (int32_t)k[l], (int32_t)k[l - 1]});
       }
   }
+}
+
+void build_transposed(const uint8_t* buf, const OpLayout& L, double* tr) {
+  std::fill(tr, tr + L.ntrans, 0.0);
+  const double* M = reinterpret_cast<const double*>(buf + L.P->off_U);  // the matrix array
+  std::vector<TransTask> tasks;
+  transpose_tasks(L, &tasks);
+  for (const TransTask& T : tasks)
+    for (int64_t c = 0; c < T.cols; ++c)
+      for (int64_t r = 0; r < T.rows; ++r) tr[T.dst + c + T.cols * r] = M[T.src + r + T.rows * c];
 }
 
 void emit_rows_N(const OpLayout& L, const RowBases& B, RowsN* R) {
