@@ -230,19 +230,33 @@ int batch_build(const void* const* bufs, const size_t* lens, int64_t count, h2_b
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_mat), sizeof(double) * std::max<int64_t>(mat, 1)), "hipMalloc(arena)");
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_trans), sizeof(double) * std::max<int64_t>(trans, 1)), "hipMalloc(arena)");
   std::vector<int32_t> pinv(std::max<int64_t>(pin, 1));
-  std::vector<double> tr;
+  // the transposed bases are made on the device from the uploaded matrix
+  // data: every operator's blocks, at its arena offsets
+  std::vector<TransTask> tasks, ti;
   for (int64_t i = 0; i < count; ++i) {
     const uint8_t* bi = static_cast<const uint8_t*>(bufs[i]);
     if (lay[i].nmat)
       HIP_TRYB(hipMemcpy(b->d_mat + base[i].mat, bi + P[i].off_U, sizeof(double) * lay[i].nmat,
                          hipMemcpyHostToDevice), "hipMemcpy(arena)");
     if (lay[i].ntrans) {
-      tr.assign(lay[i].ntrans, 0.0);
-      build_transposed(bi, lay[i], tr.data());
-      HIP_TRYB(hipMemcpy(b->d_trans + base[i].trans, tr.data(), sizeof(double) * lay[i].ntrans,
-                         hipMemcpyHostToDevice), "hipMemcpy(arena)");
+      transpose_tasks(lay[i], &ti);
+      for (TransTask& t : ti) {
+        t.src += base[i].mat;
+        t.dst += base[i].trans;
+        tasks.push_back(t);
+      }
     }
     for (int64_t j = 0; j < P[i].n; ++j) pinv[b->pinv_off[i] + P[i].perm[j]] = (int32_t)j;
+  }
+  HIP_TRYB(hipMemset(b->d_trans, 0, sizeof(double) * std::max<int64_t>(trans, 1)), "hipMemset(arena)");
+  if (!tasks.empty()) {
+    TransTask* d_tasks = nullptr;
+    HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&d_tasks), sizeof(TransTask) * tasks.size()), "hipMalloc(tasks)");
+    hipError_t e = hipMemcpy(d_tasks, tasks.data(), sizeof(TransTask) * tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_transpose_tasks(d_tasks, (int64_t)tasks.size(), b->d_mat, b->d_trans, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(d_tasks);
+    if (e != hipSuccess) return hip_fail_b(e, "transposed basis copies");
   }
   HIP_TRYB(hipMalloc(reinterpret_cast<void**>(&b->d_pinv), sizeof(int32_t) * pinv.size()), "hipMalloc(pinv)");
   HIP_TRYB(hipMemcpy(b->d_pinv, pinv.data(), sizeof(int32_t) * pinv.size(), hipMemcpyHostToDevice), "hipMemcpy");
